@@ -1,0 +1,134 @@
+"""Benchmark: -2logL evaluations per second on one MI355X.
+
+Workload: n=4096 points in d=8 (Latin-hypercube-like design, smooth response
+plus noise), p=1.95, nugget 1e-6, a batch of 128 thetas log-uniform on
+[0.05, 20]^8.  One step = one gp_nll_batch call over the 128 thetas: the
+whole hot path (correlation build, blocked Cholesky, log-determinant, solves
+and reductions) with every input already resident in HBM.
+
+Prints one JSON line.  `roofline` reports the dominant kernel (the FP64-MFMA
+trailing SYRK/GEMM update): algorithmic FLOPs of its launches in the timed
+steps over their summed HIP-event durations, recorded by the library on the
+stream the kernels run on.  `cpu_baseline` times the plain C oracle (FP64,
+one theta per thread) on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "-2logL evals/sec at n=4096,d=8 (mixed vs FP64 GPU); p50/p99 request latency"
+FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
+HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--batch", type=int, default=128)
+    ap.add_argument("--n", type=int, default=4096)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0,
+                    help="oracle threads (default: min(16, available cores))")
+    return ap.parse_args()
+
+
+def cpu_baseline(w, threads):
+    """Time the FP64 oracle on `threads` thetas of the same workload, one per
+    thread (about 20-40 s of wall time at n=4096)."""
+    import oracle
+    oracle.build()
+    th = w.theta[:threads]
+    t0 = time.perf_counter()
+    r = oracle.nll_batch(w.X, w.y, th, w.p, w.delta, nthreads=threads)
+    dt = time.perf_counter() - t0
+    assert (r.info == 0).all()
+    return {"value": len(th) / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(th)} of the {w.B} thetas of the same n={w.n}, d={w.d} workload, "
+                      f"one theta per thread, {dt:.1f} s wall"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); every evaluation is "
+              "independent, so more GPUs would split the theta batch (not built).", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1203_1269_amd import binding, inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    w = inputs.fp64_at_scale(n=args.n, B=args.batch)
+    ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
+    theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
+    ws = binding.alloc_workspace(binding.workspace_bytes(w.n, w.d, w.B), dev)
+    out = torch.empty((w.B, 5), dtype=torch.float64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        binding.nll_batch_raw(ds, theta, ws, out, stream=stream)
+    torch.cuda.synchronize()
+
+    # timed region; the library records per-launch events on the same stream
+    binding.profile_begin(max_launches=4000 * max(1, args.steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        binding.nll_batch_raw(ds, theta, ws, out, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kstats = binding.profile_end()
+
+    res = {k: v.cpu() for k, v in binding.unpack_results(out).items()}
+    n_ok = int((res["info"] == 0).sum())
+    evals = w.B * args.steps / dt
+    ms_step = dt / args.steps * 1e3
+
+    sy = kstats["syrk_update"]
+    achieved = sy["flops"] / (sy["ms"] * 1e-3)
+    factor_flops = w.n ** 3 / 3.0
+    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
+                   "gflop_per_step": v["flops"] / args.steps / 1e9,
+                   "gbyte_per_step": v["bytes"] / args.steps / 1e9}
+               for k, v in kstats.items()}
+    line = {
+        "metric": METRIC,
+        "value": evals,
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "n": w.n, "d": w.d, "batch": w.B, "p": w.p,
+                   "delta": w.delta, "prec": "fp64", "seed": w.seed},
+        "roofline": {"bound": "mfma", "kernel": "syrk_update", "achieved": achieved / 1e12,
+                     "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
+                     "frac": achieved / FP64_MFMA_PEAK, "traffic": None},
+        "factorization_frac_of_fp64_peak": factor_flops * evals / FP64_MFMA_PEAK,
+        "results_ok": n_ok,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        line["cpu_baseline"] = cpu_baseline(w, threads)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

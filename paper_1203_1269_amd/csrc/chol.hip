@@ -1,0 +1,385 @@
+// Blocked right-looking Cholesky R_delta = L L' in FP64 for a batch of
+// matrices (the factorisation the paper uses for the determinant and the
+// solves, Sec. 2 and Sec. 3 "CPU implementation"; its GPU code used a
+// library LU instead, Sec. 3).
+//
+// Two-level blocking:
+//   outer panels of OUTER_NB = 256 columns; each is factored by four inner
+//   steps of TB = 64 columns, left-looking inside the panel (update of the
+//   64-column block by the panel's earlier blocks, POTRF of its 64 x 64
+//   diagonal tile, TRSM of the rows below it); then the trailing matrix
+//   receives one right-looking rank-256 update (SYRK/GEMM on FP64 MFMA).
+// The rank-256 trailing update carries ~90% of the n^3/3 flops.  With K = 256
+// each 128 x 128 output tile does 8.4 MFLOP per 256 KiB of C traffic, which
+// keeps it above the FP64 ridge of the chip (78.6 TFLOP/s over 8 TB/s).
+#include <math.h>
+
+#include "kernels.hpp"
+
+namespace gpk {
+
+namespace {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+
+// Quad broadcast: every lane of each group of 4 lanes receives the value of
+// lane Q of its group (DPP quad_perm, no LDS traffic).
+template <int Q>
+__device__ __forceinline__ double quad_bcast_q(double v)
+{
+    constexpr int ctrl = Q * 0x55;   // quad_perm [Q, Q, Q, Q]
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ __forceinline__ double quad_bcast(double v, int q)
+{
+    switch (q & 3) {
+    case 0: return quad_bcast_q<0>(v);
+    case 1: return quad_bcast_q<1>(v);
+    case 2: return quad_bcast_q<2>(v);
+    default: return quad_bcast_q<3>(v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// POTRF of one 64 x 64 diagonal tile per matrix.  Right-looking, column by
+// column: L_jj = sqrt(a_jj), L_ij = a_ij / L_jj, then the rank-1 update of the
+// columns right of j.  The tile lives in registers: 4 lanes per row, lane q
+// of row r holds columns q, q+4, ..., q+60.  Per column one LDS broadcast
+// (double-buffered, one barrier).  Division by the pivot is a multiplication
+// by its reciprocal.  Also writes 2 sum_j ln L_jj of the tile (wave-level
+// reduction) and the first failing pivot (1-based, global) into info.
+
+constexpr int PO_THREADS = 256;
+
+__global__ __launch_bounds__(PO_THREADS)
+void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
+                       int32_t *__restrict__ info, double *__restrict__ lpart, int nparts)
+{
+    __shared__ double col[2][TB];
+    __shared__ double dg[TB];
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int q = tid & 3, r = tid >> 2;
+    double *A = A0 + (size_t)b * bstride + (size_t)c0 + (size_t)c0 * lda;
+
+    double a[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) a[m] = A[(size_t)r + (size_t)(q + 4 * m) * lda];
+
+    int first_bad = 0;
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+        const int qj = j & 3, mj = j >> 2;
+        double *cb = col[j & 1];
+        if (q == qj) cb[r] = a[mj];
+        __syncthreads();
+        const double piv = cb[j];
+        if (!(piv > 0.0) && first_bad == 0) first_bad = c0 + j + 1;
+        const double l = sqrt(piv);
+        const double linv = 1.0 / l;
+        const double lrj = cb[r] * linv;
+        if (q == qj) a[mj] = (r == j) ? l : ((r > j) ? lrj : 0.0);
+        if (tid == 0) dg[j] = l;
+#pragma unroll
+        for (int m = mj; m < 16; ++m) {
+            const int c = q + 4 * m;
+            if (m > mj || q > qj) a[m] = fma(-lrj, cb[c] * linv, a[m]);
+        }
+    }
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+        const int c = q + 4 * m;
+        A[(size_t)r + (size_t)c * lda] = (r >= c) ? a[m] : 0.0;
+    }
+    __syncthreads();
+    if (tid < TB) {
+        double v = log(dg[tid]);
+#pragma unroll
+        for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+        if (tid == 0) {
+            lpart[(size_t)b * nparts + c0 / TB] = 2.0 * v;
+            if (first_bad != 0 && info[b] == 0) info[b] = first_bad;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// TRSM: rows below the diagonal tile, X L_kk' = A, i.e. per row
+// x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj, right-looking over j.
+// 4 lanes per row group (lane q holds columns q, q+4, ..., q+60); each lane
+// group holds TR_RPL rows (every L value read from LDS feeds TR_RPL FMAs).  The solved x_j is passed to the other lanes of the group by a
+// DPP quad broadcast; L_kk sits in LDS permuted so that the values a lane
+// needs for one j are contiguous.
+
+constexpr int TR_THREADS = 256;
+constexpr int TR_RPL = 1;
+constexpr int TR_ROWS = TR_THREADS / 4 * TR_RPL;
+
+__global__ __launch_bounds__(TR_THREADS)
+void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int c0)
+{
+    __shared__ double Lp[TB][4][16];   // Lp[j][q][m] = L(q + 4m, j)
+    __shared__ double rinv[TB];
+    const int b = blockIdx.y;
+    const int tid = threadIdx.x;
+    double *A = A0 + (size_t)b * bstride;
+    {
+        // all 16 loads in flight before the LDS stores
+        double t[TB * TB / TR_THREADS];
+#pragma unroll
+        for (int k = 0; k < TB * TB / TR_THREADS; ++k) {
+            const int e = tid + k * TR_THREADS, rr = e % TB, c = e / TB;
+            t[k] = A[(size_t)(c0 + rr) + (size_t)(c0 + c) * lda];
+        }
+#pragma unroll
+        for (int k = 0; k < TB * TB / TR_THREADS; ++k) {
+            const int e = tid + k * TR_THREADS, rr = e % TB, c = e / TB;
+            Lp[c][rr & 3][rr >> 2] = t[k];
+        }
+    }
+    __syncthreads();
+    if (tid < TB) rinv[tid] = 1.0 / Lp[tid][tid & 3][tid >> 2];
+    __syncthreads();
+    const int q = tid & 3;
+    // rows base + g + 64 i, i < TR_RPL; np and base are multiples of 64, so
+    // each i is valid or invalid for the whole workgroup
+    const int base = c0 + TB + blockIdx.x * TR_ROWS + (tid >> 2);
+    double x[TR_RPL][16];
+    double *p[TR_RPL];
+#pragma unroll
+    for (int i = 0; i < TR_RPL; ++i) {
+        const int row = base + 64 * i;
+        p[i] = A + (size_t)min(row, np - 1) + (size_t)(c0 + q) * lda;
+#pragma unroll
+        for (int m = 0; m < 16; ++m) x[i][m] = (row < np) ? p[i][(size_t)(4 * m) * lda] : 0.0;
+    }
+#pragma unroll
+    for (int j = 0; j < TB; ++j) {
+        const int qj = j & 3, mj = j >> 2;
+        const double rj = rinv[j];
+        double xj[TR_RPL];
+#pragma unroll
+        for (int i = 0; i < TR_RPL; ++i) {
+            xj[i] = quad_bcast(x[i][mj] * rj, qj);
+            if (q == qj) x[i][mj] = xj[i];
+        }
+#pragma unroll
+        for (int m = mj; m < 16; ++m) {
+            const double l = Lp[j][q][m];
+            if (m > mj || q > qj) {
+#pragma unroll
+                for (int i = 0; i < TR_RPL; ++i) x[i][m] = fma(-xj[i], l, x[i][m]);
+            }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < TR_RPL; ++i) {
+        if (base + 64 * i < np) {
+#pragma unroll
+            for (int m = 0; m < 16; ++m) p[i][(size_t)(4 * m) * lda] = x[i][m];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// SYRK/GEMM update on FP64 MFMA (v_mfma_f64_16x16x4f64).
+// Work item = (matrix, 128 x 128 output tile on or below the diagonal of the
+// column range).  Each of the 4 waves owns a 64 x 64 quadrant = 4 x 4 MFMA
+// blocks of 16 x 16; quadrants above the diagonal or outside the range idle.
+// Operand layout of the 16x16x4 f64 MFMA (wave64, measured on gfx950):
+// A[i][k] in lane i + 16k, B[k][j] in lane j + 16k, and D[i][j] in lane
+// j + 16 (i % 4), element i / 4.  The A rows are fed permuted,
+// MFMA row i <- matrix row 4 (i % 4) + i / 4, so that the four accumulator
+// elements of lane l are the four consecutive matrix rows 4 (l / 16) + 0..3
+// of column l % 16: C is loaded and stored with 2 x 16-byte accesses per
+// lane.  The accumulators start at -C and the chain adds A(r,k) A(c,k), so
+// the result C - sum_k A(r,k) A(c,k) is stored with one sign flip.  Two
+// fragment sets alternate: each is reloaded for the k-step after next as
+// soon as its 16 MFMAs are issued.
+// Work items are mapped XCD-major: blocks are dispatched round-robin over the
+// 8 XCDs, so block id b runs on XCD b % 8; consecutive work items (same
+// matrix) are given to the same XCD and share its L2 for the panel reads.
+
+constexpr int SY_THREADS = 256;
+constexpr int NXCD = 8;
+
+// WR x WC waves of 64 x 64: <2,2> = 128 x 128 tiles over a lower-triangular
+// column range; <4,1> = 256 x 64 tiles over a single 64-wide column block.
+template <int WR, int WC>
+__global__ __launch_bounds__(SY_THREADS, 2)
+void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int cs,
+                        int ce, int kc0, int K, int NR, int ntiles, int batch)
+{
+    constexpr int TR = 64 * WR, TC = 64 * WC;
+    const int W = ntiles * batch;
+    const int per = (W + NXCD - 1) / NXCD;
+    const int bid = blockIdx.x;
+    const int work = (bid % NXCD) * per + bid / NXCD;
+    if (work >= W) return;
+    const int b = work / ntiles;
+    int t = work - b * ntiles;
+    int jt = 0, it = t;
+    if (WC > 1) {
+        while (t >= NR - jt) { t -= NR - jt; ++jt; }
+        it = jt + t;
+    }
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int r0 = cs + TR * it + 64 * (wave / WC);
+    const int c0 = cs + TC * jt + 64 * (wave % WC);
+    if (r0 >= np || c0 >= ce || r0 < c0) return;   // no barriers below
+
+    double *A = A0 + (size_t)b * bstride;
+    const int li = lane & 15, lk = lane >> 4;
+    const int pli = 4 * (li & 3) + (li >> 2);   // permuted A row of this lane
+
+    // operand pointers and the first two k-steps of fragments go out first
+    const double *pa = A + (size_t)(r0 + pli) + (size_t)(kc0 + lk) * lda;
+    const double *pb = A + (size_t)(c0 + li) + (size_t)(kc0 + lk) * lda;
+    const size_t step4 = (size_t)4 * lda;
+    double a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
+
+    // accumulators start at -C and gather +A(r,k) A(c,k): no per-step negation
+    dbl4 acc[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const double *p = A + (size_t)(r0 + 16 * rb + 4 * lk) + (size_t)(c0 + 16 * cb + li) * lda;
+            dbl2 lo = *(const dbl2 *)p;
+            dbl2 hi = *(const dbl2 *)(p + 2);
+            acc[rb][cb] = -(dbl4){lo.x, lo.y, hi.x, hi.y};
+        }
+
+    // K is a multiple of 64: two k-steps per trip, each fragment set reloaded
+    // for the trip after next right after its MFMAs were issued
+    for (int kk = 0; kk < K; kk += 8) {
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[rb], b0[cb], acc[rb][cb],
+                                                                   0, 0, 0);
+        pa += 2 * step4;
+        pb += 2 * step4;
+        if (kk + 8 < K) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[rb], b1[cb], acc[rb][cb],
+                                                                   0, 0, 0);
+        if (kk + 12 < K) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
+        }
+    }
+
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            double *p = A + (size_t)(r0 + 16 * rb + 4 * lk) + (size_t)(c0 + 16 * cb + li) * lda;
+            dbl4 v = -acc[rb][cb];
+            *(dbl2 *)p = (dbl2){v.x, v.y};
+            *(dbl2 *)(p + 2) = (dbl2){v.z, v.w};
+        }
+}
+
+__global__ void logdet_sum_kernel(const double *__restrict__ lpart, int nparts, int batch,
+                                  double *__restrict__ logdet)
+{
+    const int b = blockIdx.x;
+    double v = 0.0;
+    for (int q = threadIdx.x; q < nparts; q += 64) v += lpart[(size_t)b * nparts + q];
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (threadIdx.x == 0) logdet[b] = v;
+}
+
+}  // namespace
+
+void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int batch, int32_t *info,
+                       double *lpart, int nparts, hipStream_t s)
+{
+    ProfScope ps(K_POTRF_DIAG, TB * TB * TB / 3.0 * batch, 16.0 * TB * TB * batch, s);
+    potrf_diag_kernel<<<batch, PO_THREADS, 0, s>>>(A, lda, bstride, c0, info, lpart, nparts);
+}
+
+void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int batch,
+                       hipStream_t s)
+{
+    int rows = np - (c0 + TB);
+    if (rows <= 0) return;
+    ProfScope ps(K_TRSM_PANEL, (double)rows * TB * TB * batch,
+                 (16.0 * rows * TB + 8.0 * TB * TB) * batch, s);
+    dim3 grid((rows + TR_ROWS - 1) / TR_ROWS, batch);
+    trsm_panel_kernel<<<grid, TR_THREADS, 0, s>>>(A, lda, bstride, np, c0);
+}
+
+void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce, int kc0,
+                        int K, int batch, hipStream_t s)
+{
+    if (ce <= cs || K <= 0) return;
+    const double entries = (double)(ce - cs) * np - 0.5 * (double)(cs + ce - 1) * (ce - cs);
+    // left-looking updates of one 64-column block inside an outer panel are
+    // reported apart from the rank-256 trailing updates
+    const bool block64 = (ce - cs) == TB;
+    ProfScope ps(block64 ? K_SYRK_PANEL : K_SYRK_UPDATE, 2.0 * K * entries * batch,
+                 (16.0 * entries + 8.0 * (double)(np - cs) * K) * batch, s);
+    int NR, ntiles;
+    if (block64) {
+        NR = (np - cs + 255) / 256;
+        ntiles = NR;
+    } else {
+        NR = (np - cs + 127) / 128;
+        const int NC = (ce - cs + 127) / 128;
+        ntiles = 0;
+        for (int jt = 0; jt < NC; ++jt) ntiles += NR - jt;
+    }
+    const long W = (long)ntiles * batch;
+    const long per = (W + NXCD - 1) / NXCD;
+    if (block64)
+        syrk_update_kernel<4, 1><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
+    else
+        syrk_update_kernel<2, 2><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
+}
+
+void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
+                  double *lpart, hipStream_t s)
+{
+    const int nparts = np / TB;
+    for (int c = 0; c < np; c += OUTER_NB) {
+        const int pe = min(c + OUTER_NB, np);
+        for (int c0 = c; c0 < pe; c0 += TB) {
+            // left-looking inside the outer panel: bring block c0 up to date
+            // with the blocks [c, c0) of the same panel, then factor it
+            if (c0 > c) launch_syrk_update(A, lda, bstride, np, c0, c0 + TB, c, c0 - c, batch, s);
+            launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, s);
+            launch_trsm_panel(A, lda, bstride, np, c0, batch, s);
+        }
+        // right-looking rank-(pe - c) update of the trailing matrix
+        if (pe < np) launch_syrk_update(A, lda, bstride, np, pe, np, c, pe - c, batch, s);
+    }
+}
+
+void launch_logdet_sum(const double *lpart, int nparts, int batch, double *logdet, hipStream_t s)
+{
+    ProfScope ps(K_LOGDET_SUM, (double)nparts * batch, 8.0 * (nparts + 1) * batch, s);
+    logdet_sum_kernel<<<batch, 64, 0, s>>>(lpart, nparts, batch, logdet);
+}
+
+}  // namespace gpk

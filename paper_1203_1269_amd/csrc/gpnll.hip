@@ -1,0 +1,134 @@
+// C ABI of libgpnll.so: argument checks, workspace carving and the launch
+// sequence of the likelihood hot path.  Declarations and contracts are in
+// include/gpnll.h.
+#include <math.h>
+#include <string.h>
+
+#include "kernels.hpp"
+
+using namespace gpk;
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+struct Layout {
+    int np;
+    size_t mat;      // offset of the matrices
+    size_t bstride;  // doubles per matrix
+    size_t lpart;    // offset of the log-det partials
+    size_t info;     // offset of info
+    size_t total;
+};
+
+bool layout_for(int n, int batch, Layout &L)
+{
+    if (n < 2 || n > GP_NMAX || batch < 1) return false;
+    L.np = pad64(n);
+    L.bstride = (size_t)L.np * L.np;
+    size_t off = 0;
+    L.mat = off;
+    off = align_up(off + L.bstride * sizeof(double) * batch);
+    L.lpart = off;
+    off = align_up(off + sizeof(double) * (size_t)(L.np / TB) * batch);
+    L.info = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)batch);
+    L.total = off;
+    return true;
+}
+
+bool dataset_ok(const gp_dataset *ds)
+{
+    if (!ds || !ds->X || !ds->y) return false;
+    if (ds->n < 2 || ds->n > GP_NMAX || ds->d < 1 || ds->d > GP_DMAX) return false;
+    if (!(ds->p > 0.0 && ds->p <= 2.0)) return false;
+    if (!(ds->delta >= 0.0) || !isfinite(ds->delta)) return false;
+    return true;
+}
+
+bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+
+gp_status launched()
+{
+    return hipGetLastError() == hipSuccess ? GP_OK : GP_ELAUNCH;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t gp_workspace_bytes(int32_t n, int32_t d, int32_t batch, int32_t prec)
+{
+    Layout L;
+    if (d < 1 || d > GP_DMAX || prec != GP_FP64) return 0;
+    if (!layout_for(n, batch, L)) return 0;
+    return L.total;
+}
+
+gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
+                       void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream)
+{
+    if (!dataset_ok(ds) || batch < 1 || !theta || !out || !ws || prec != GP_FP64)
+        return GP_EINVAL;
+    if (!aligned16(ws)) return GP_EINVAL;
+    Layout L;
+    if (!layout_for(ds->n, batch, L)) return GP_EINVAL;
+    if (ws_bytes < L.total) return GP_EWORKSPACE;
+
+    char *base = (char *)ws;
+    double *A = (double *)(base + L.mat);
+    double *lpart = (double *)(base + L.lpart);
+    int32_t *info = (int32_t *)(base + L.info);
+    const int np = L.np;
+
+    launch_init(theta, ds->d, batch, info, stream);
+    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
+                      stream);
+    factor_batch(A, np, L.bstride, np, batch, info, lpart, stream);
+    launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
+                        stream);
+    return launched();
+}
+
+gp_status gp_nll(const gp_dataset *ds, const double *theta, int32_t prec, void *ws,
+                 size_t ws_bytes, gp_result *out, hipStream_t stream)
+{
+    return gp_nll_batch(ds, 1, theta, prec, ws, ws_bytes, out, stream);
+}
+
+gp_status gp_corr_build(const gp_dataset *ds, int32_t batch, const double *theta, double *R,
+                        int32_t ldr, int32_t *info, hipStream_t stream)
+{
+    if (!dataset_ok(ds) || batch < 1 || !theta || !R || !info) return GP_EINVAL;
+    const int np = pad64(ds->n);
+    if (ldr < np) return GP_EINVAL;
+    launch_init(theta, ds->d, batch, info, stream);
+    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, R, ldr,
+                      (size_t)ldr * ldr, np, stream);
+    return launched();
+}
+
+size_t gp_cholesky_ws_bytes(int32_t n, int32_t batch)
+{
+    if (n < 1 || n > GP_NMAX || batch < 1) return 0;
+    return align_up(sizeof(double) * (size_t)(pad64(n) / TB) * batch);
+}
+
+gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda, int32_t *info,
+                            double *logdet, void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    if (n < 1 || n > GP_NMAX || batch < 1 || !A || !info || !logdet || !ws) return GP_EINVAL;
+    const int np = pad64(n);
+    if (lda < np || !aligned16(A) || (lda % 2) != 0) return GP_EINVAL;
+    if (ws_bytes < gp_cholesky_ws_bytes(n, batch)) return GP_EWORKSPACE;
+    double *lpart = (double *)ws;
+    const size_t bstride = (size_t)lda * lda;
+    launch_pad_identity(A, lda, bstride, n, np, batch, stream);
+    factor_batch(A, lda, bstride, np, batch, info, lpart, stream);
+    launch_logdet_sum(lpart, np / TB, batch, logdet, stream);
+    return launched();
+}
+
+}  // extern "C"

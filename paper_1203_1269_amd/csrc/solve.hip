@@ -1,0 +1,161 @@
+// Forward solves L [a b] = [1 y] and the reductions of eq. 3-4 (paper Sec. 2):
+//   mu = (a.b)/(a.a),  Q = |b - mu a|^2 (two-pass),  sigma2 = Q/n,
+//   nll = log|R| + n ln(sigma2),  log|R| = sum of the per-tile partials.
+// One workgroup per matrix.  The solve is blocked by 64 rows: the 16 waves
+// split the columns left of the block (GEMV with both right-hand sides, each
+// wave reading whole 512-byte column segments of L), then wave 0 finishes the
+// 64 x 64 triangular block with lane-to-lane broadcasts.  The solution
+// vectors live in LDS (2 n_pad doubles), so n_pad <= 8192.
+// The kernel streams the n^2/2 lower entries of L once: HBM bound.
+#include <math.h>
+
+#include "kernels.hpp"
+
+namespace gpk {
+
+namespace {
+
+constexpr int SV_THREADS = 1024;
+constexpr int SV_WAVES = SV_THREADS / 64;
+constexpr int SV_UNROLL = 8;
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(SV_THREADS)
+void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride, int np, int n,
+                         const double *__restrict__ y, const double *__restrict__ lpart,
+                         int nparts, const int32_t *__restrict__ info,
+                         gp_result *__restrict__ out)
+{
+    extern __shared__ double zs[];          // z0[np], z1[np]
+    __shared__ double part[SV_WAVES][2][64];
+    __shared__ double red[SV_WAVES][3];
+    double *z0 = zs, *z1 = zs + np;
+
+    const int b = blockIdx.x;
+    const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+    const double *A = A0 + (size_t)b * bstride;
+    const int T = np / TB;
+
+    for (int ib = 0; ib < T; ++ib) {
+        const int r = ib * TB + lane;
+        const int ncol = ib * TB;
+        double s0 = 0.0, s1 = 0.0;
+        const double *pr = A + r;
+        int c = wave;
+        for (; c + (SV_UNROLL - 1) * SV_WAVES < ncol; c += SV_UNROLL * SV_WAVES) {
+            double v[SV_UNROLL];
+#pragma unroll
+            for (int u = 0; u < SV_UNROLL; ++u) v[u] = pr[(size_t)(c + u * SV_WAVES) * lda];
+#pragma unroll
+            for (int u = 0; u < SV_UNROLL; ++u) {
+                s0 = fma(v[u], z0[c + u * SV_WAVES], s0);
+                s1 = fma(v[u], z1[c + u * SV_WAVES], s1);
+            }
+        }
+        for (; c < ncol; c += SV_WAVES) {
+            double v = pr[(size_t)c * lda];
+            s0 = fma(v, z0[c], s0);
+            s1 = fma(v, z1[c], s1);
+        }
+        part[wave][0][lane] = s0;
+        part[wave][1][lane] = s1;
+        __syncthreads();
+        if (wave == 0) {
+            double t0 = 0.0, t1 = 0.0;
+            for (int w = 0; w < SV_WAVES; ++w) { t0 += part[w][0][lane]; t1 += part[w][1][lane]; }
+            t0 = ((r < n) ? 1.0 : 0.0) - t0;
+            t1 = ((r < n) ? y[r] : 0.0) - t1;
+            double Lrow[TB];
+            const double *pd = A + r + (size_t)ib * TB * lda;
+#pragma unroll
+            for (int j = 0; j < TB; ++j) Lrow[j] = pd[(size_t)j * lda];
+#pragma unroll
+            for (int j = 0; j < TB; ++j) {
+                // lane j holds the finished right-hand sides of row j
+                const double q0 = __shfl(t0 / Lrow[j], j, 64);
+                const double q1 = __shfl(t1 / Lrow[j], j, 64);
+                if (lane == j) { t0 = q0; t1 = q1; }
+                else if (lane > j) { t0 = fma(-Lrow[j], q0, t0); t1 = fma(-Lrow[j], q1, t1); }
+            }
+            z0[r] = t0;
+            z1[r] = t1;
+        }
+        __syncthreads();
+    }
+
+    // aa = a.a, ab = a.b over the n real rows
+    double aa = 0.0, ab = 0.0;
+    for (int r = tid; r < n; r += SV_THREADS) { aa = fma(z0[r], z0[r], aa); ab = fma(z0[r], z1[r], ab); }
+    aa = wave_sum(aa);
+    ab = wave_sum(ab);
+    if (lane == 0) { red[wave][0] = aa; red[wave][1] = ab; }
+    __syncthreads();
+    aa = 0.0; ab = 0.0;
+    for (int w = 0; w < SV_WAVES; ++w) { aa += red[w][0]; ab += red[w][1]; }
+    const double mu = ab / aa;
+    __syncthreads();
+    double Q = 0.0;
+    for (int r = tid; r < n; r += SV_THREADS) {
+        const double e = fma(-mu, z0[r], z1[r]);
+        Q = fma(e, e, Q);
+    }
+    Q = wave_sum(Q);
+    double ld = 0.0;
+    for (int q = tid; q < nparts; q += SV_THREADS) ld += lpart[(size_t)b * nparts + q];
+    ld = wave_sum(ld);
+    if (lane == 0) { red[wave][0] = Q; red[wave][2] = ld; }
+    __syncthreads();
+    if (tid == 0) {
+        Q = 0.0; ld = 0.0;
+        for (int w = 0; w < SV_WAVES; ++w) { Q += red[w][0]; ld += red[w][2]; }
+        gp_result res;
+        res.ir_iters = 0;
+        int inf = info[b];
+        if (inf != 0) {
+            res.logdet = res.mu = res.sigma2 = res.nll = NAN;
+            res.info = inf;
+        } else if (Q == 0.0) {
+            res.logdet = ld;
+            res.mu = mu;
+            res.sigma2 = 0.0;
+            res.nll = -INFINITY;
+            res.info = -1;
+        } else {
+            const double s2 = Q / (double)n;
+            res.logdet = ld;
+            res.mu = mu;
+            res.sigma2 = s2;
+            res.nll = ld + (double)n * log(s2);
+            res.info = 0;
+        }
+        out[b] = res;
+    }
+}
+
+}  // namespace
+
+void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n, const double *y,
+                         const double *lpart, int nparts, const int32_t *info, int batch,
+                         gp_result *out, hipStream_t s)
+{
+    static bool attr_set = false;
+    const size_t shm = (size_t)2 * np * sizeof(double);
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)solve_reduce_kernel,
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)(2 * GP_NMAX * sizeof(double)));
+        attr_set = true;
+    }
+    const double lower = 0.5 * (double)np * (np + 1);
+    ProfScope ps(K_SOLVE_REDUCE, 4.0 * lower * batch, (8.0 * lower + 16.0 * n) * batch, s);
+    solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
+                                                       info, out);
+}
+
+}  // namespace gpk

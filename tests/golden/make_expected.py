@@ -1,0 +1,71 @@
+"""Write oracle values for sampled thetas of the full-size workloads.
+
+Calls only the CPU oracle (80-bit and FP64 builds, plus LAPACK on the
+oracle's R to measure the FP64 rounding spread) on the seeded inputs of
+paper_1203_1269_amd.inputs; the GPU path is not involved.  Usage:
+    python tests/golden/make_expected.py fp64_n4096_d8
+"""
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1203_1269_amd import inputs  # noqa: E402
+
+sys.path.insert(0, os.path.dirname(HERE))
+from parity_util import lapack_fp64  # noqa: E402
+
+WORKLOADS = {
+    "fp64_n4096_d8": inputs.fp64_at_scale,
+    "mixed_n8192_d10": inputs.mixed_at_scale,
+}
+
+
+def sample_indices(theta, k):
+    """The theta with the smallest and the largest norm plus evenly spaced others."""
+    norms = np.linalg.norm(np.log(theta), axis=1)
+    idx = {int(np.argmin(np.sum(theta, axis=1))), int(np.argmax(np.sum(theta, axis=1)))}
+    for q in np.linspace(0, theta.shape[0] - 1, k):
+        if len(idx) >= k:
+            break
+        idx.add(int(q))
+    _ = norms
+    return sorted(idx)
+
+
+def main(name, k=4):
+    w = WORKLOADS[name]()
+    idx = sample_indices(w.theta, k)
+    t0 = time.time()
+    th = w.theta[idx]
+    r64 = oracle.nll_batch(w.X, w.y, th, w.p, w.delta)
+    r80 = oracle.nll_batch(w.X, w.y, th, w.p, w.delta, extended=True)
+    lap = lapack_fp64(w.X, w.y, th, w.p, w.delta)
+    sc = {"logdet": 1.0, "nll": 1.0, "mu": float(np.std(w.y)), "sigma2": 0.0}
+    samples = []
+    for q, t in enumerate(idx):
+        rec = {"index": t, "theta": th[q].tolist(), "info": int(r80.info[q]), "f80": {}, "f64": {},
+               "err64": {}, "err64_lapack": {}}
+        for key in ("logdet", "mu", "sigma2", "nll"):
+            a, b = float(getattr(r64, key)[q]), float(getattr(r80, key)[q])
+            rec["f80"][key] = b
+            rec["f64"][key] = a
+            rec["err64"][key] = abs(a - b) / max(abs(b), sc[key])
+            rec["err64_lapack"][key] = abs(float(lap[key][q]) - b) / max(abs(b), sc[key])
+        samples.append(rec)
+    out = {"workload": name, "seed": w.seed, "n": w.n, "d": w.d, "B": w.B, "p": w.p,
+           "delta": w.delta, "samples": samples, "oracle_seconds": time.time() - t0}
+    path = os.path.join(HERE, f"{name}_expected.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"])
+
+
+if __name__ == "__main__":
+    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 4)

@@ -1,0 +1,113 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/gpnll.h declares, and rejects invalid arguments before
+touching the device."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "gpnll.h")
+LIB = os.path.join(ROOT, "paper_1203_1269_amd", "libgpnll.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:gp_status|size_t|int|void)\s+\**\s*(gp_\w+)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        from paper_1203_1269_amd import build
+        build.build()
+    from paper_1203_1269_amd import binding
+    return binding.lib()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for required in ("gp_nll", "gp_nll_batch", "gp_workspace_bytes", "gp_corr_build",
+                     "gp_cholesky_batch", "gp_cholesky_ws_bytes"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    exported = set(re.findall(r"\s[TW]\s+(\w+)$", out, flags=re.M))
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_result_struct_layout():
+    from paper_1203_1269_amd import binding
+    assert ctypes.sizeof(binding.GPResult) == 40
+    assert ctypes.sizeof(binding.GPDataset) == 40
+    assert binding.header_constant("GP_NMAX") == 8192
+    assert binding.header_constant("GP_DMAX") == 32
+
+
+def test_workspace_sizing(lib):
+    from paper_1203_1269_amd import binding
+    ws = binding.workspace_bytes(4096, 8, 128)
+    assert ws >= 128 * 4096 * 4096 * 8
+    assert ws < 128 * 4096 * 4096 * 8 + (1 << 22)
+    assert binding.workspace_bytes(200, 2, 64) >= 64 * 256 * 256 * 8
+    assert lib.gp_workspace_bytes(1, 2, 1, 0) == 0        # n < 2
+    assert lib.gp_workspace_bytes(8193, 2, 1, 0) == 0     # n > GP_NMAX
+    assert lib.gp_workspace_bytes(100, 0, 1, 0) == 0      # d < 1
+    assert lib.gp_workspace_bytes(100, 33, 1, 0) == 0     # d > GP_DMAX
+    assert lib.gp_workspace_bytes(100, 2, 0, 0) == 0      # empty batch
+    assert lib.gp_workspace_bytes(100, 2, 1, 7) == 0      # unknown precision
+
+
+def _ds(X=1 << 20, y=1 << 21, n=100, d=2, p=2.0, delta=1e-6):
+    from paper_1203_1269_amd import binding
+    return binding.GPDataset(X, y, n, d, p, delta)
+
+
+@pytest.mark.parametrize("kw", [dict(n=1), dict(n=8193), dict(d=0), dict(d=33), dict(p=0.0),
+                                dict(p=2.5), dict(p=float("nan")), dict(delta=-1e-9),
+                                dict(delta=float("inf")), dict(X=0), dict(y=0)])
+def test_invalid_dataset_rejected_on_host(lib, kw):
+    from paper_1203_1269_amd import binding
+    ds = _ds(**kw)
+    vp = ctypes.c_void_p
+    st = lib.gp_nll_batch(ctypes.byref(ds), 4, vp(1 << 22), 0, vp(1 << 23), 1 << 40, vp(1 << 24), None)
+    assert st == binding.GP_EINVAL
+    st = lib.gp_corr_build(ctypes.byref(ds), 4, vp(1 << 22), vp(1 << 23), 256, vp(1 << 24), None)
+    assert st == binding.GP_EINVAL
+
+
+def test_invalid_call_arguments_rejected_on_host(lib):
+    from paper_1203_1269_amd import binding
+    ds = _ds()
+    vp = ctypes.c_void_p
+    need = lib.gp_workspace_bytes(100, 2, 4, 0)
+    assert lib.gp_nll_batch(ctypes.byref(ds), 0, vp(1 << 22), 0, vp(1 << 23), need, vp(1 << 24), None) == binding.GP_EINVAL
+    assert lib.gp_nll_batch(ctypes.byref(ds), 4, None, 0, vp(1 << 23), need, vp(1 << 24), None) == binding.GP_EINVAL
+    assert lib.gp_nll_batch(ctypes.byref(ds), 4, vp(1 << 22), 0, None, need, vp(1 << 24), None) == binding.GP_EINVAL
+    assert lib.gp_nll_batch(ctypes.byref(ds), 4, vp(1 << 22), 0, vp(1 << 23), need, None, None) == binding.GP_EINVAL
+    assert lib.gp_nll_batch(ctypes.byref(ds), 4, vp(1 << 22), 5, vp(1 << 23), need, vp(1 << 24), None) == binding.GP_EINVAL
+    assert lib.gp_nll_batch(ctypes.byref(ds), 4, vp(1 << 22), 0, vp((1 << 23) + 8), need, vp(1 << 24), None) == binding.GP_EINVAL
+    assert lib.gp_nll_batch(ctypes.byref(ds), 4, vp(1 << 22), 0, vp(1 << 23), need - 1, vp(1 << 24), None) == binding.GP_EWORKSPACE
+    assert lib.gp_nll_batch(None, 4, vp(1 << 22), 0, vp(1 << 23), need, vp(1 << 24), None) == binding.GP_EINVAL
+    # Cholesky entry point
+    assert lib.gp_cholesky_batch(100, 2, vp(1 << 22), 100, vp(1 << 23), vp(1 << 24), vp(1 << 25), 1 << 20, None) == binding.GP_EINVAL  # lda < 128
+    assert lib.gp_cholesky_batch(100, 2, vp(1 << 22), 129, vp(1 << 23), vp(1 << 24), vp(1 << 25), 1 << 20, None) == binding.GP_EINVAL  # odd lda
+    assert lib.gp_cholesky_batch(100, 2, vp(1 << 22), 128, vp(1 << 23), vp(1 << 24), vp(1 << 25), 0, None) == binding.GP_EWORKSPACE
+    assert lib.gp_corr_build(ctypes.byref(ds), 4, vp(1 << 22), vp(1 << 23), 100, vp(1 << 24), None) == binding.GP_EINVAL  # ldr < 128
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    from paper_1203_1269_amd import binding
+    monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
+    monkeypatch.setattr(binding, "_lib", None)
+    with pytest.raises(ImportError):
+        binding.lib()
