@@ -37,6 +37,10 @@ def parse():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
+    ap.add_argument("--serving-requests", type=int, default=5000)
+    ap.add_argument("--serving-arena-gb", type=float, default=16.0)
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (default: min(16, available cores))")
     return ap.parse_args()
@@ -55,6 +59,37 @@ def cpu_baseline(w, threads):
     return {"value": len(th) / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(th)} of the {w.B} thetas of the same n={w.n}, d={w.d} workload, "
                       f"one theta per thread, {dt:.1f} s wall"}
+
+
+def serving_leg(args, dev):
+    """64 resident datasets (n uniform over multiples of 64 in [256, 6144],
+    d in 2..12, p in {1.5, 1.95, 2}); a closed-loop burst measures the
+    saturation throughput, then Poisson streams at 0.5x and 0.9x of it are
+    replayed open-loop with per-request latency."""
+    import numpy as np
+    from paper_1203_1269_amd import binding, inputs, serving
+    sets = inputs.serving_datasets()
+    ds = [binding.Dataset(s.X, s.y, s.p, s.delta, device=dev) for s in sets]
+    arena = int(args.serving_arena_gb * (1 << 30))
+    srv = serving.Server(ds, arena_bytes=arena, max_batch=16, nstreams=8)
+    N = args.serving_requests
+    burst = inputs.serving_requests(sets, count=min(N, 1000), rate=1e9, seed=7)
+    lat, _, bsz, wall = serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
+                                       [r[1] for r in burst])
+    sat = len(burst) / wall
+    out = {"datasets": len(ds), "arena_gb": args.serving_arena_gb, "max_batch": 16, "streams": 8,
+           "saturation_evals_per_s": sat}
+    for frac in (0.5, 0.9):
+        reqs = inputs.serving_requests(sets, count=N, rate=frac * sat, seed=8)
+        lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                             [r[1] for r in reqs])
+        summ = serving.latency_summary(lat, wall)
+        summ["offered_rate"] = frac * sat
+        summ["mean_batch"] = float(np.mean(bsz))
+        summ["failed"] = int(sum(1 for r in res if r["info"] != 0))
+        out[f"poisson_{frac}"] = summ
+    srv.close()
+    return out
 
 
 def main():
@@ -76,22 +111,40 @@ def main():
     out = torch.empty((w.B, 5), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
 
-    for _ in range(args.warmup):
-        binding.nll_batch_raw(ds, theta, ws, out, stream=stream)
-    torch.cuda.synchronize()
+    def timed(prec):
+        for _ in range(args.warmup):
+            binding.nll_batch_raw(ds, theta, ws, out, prec=prec, stream=stream)
+        torch.cuda.synchronize()
+        # timed region; the library records per-launch events on the same stream
+        binding.profile_begin(max_launches=4000 * max(1, args.steps))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            binding.nll_batch_raw(ds, theta, ws, out, prec=prec, stream=stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        kstats = binding.profile_end()
+        res = {k: v.cpu().numpy().copy() for k, v in binding.unpack_results(out).items()}
+        return dt, kstats, res
 
-    # timed region; the library records per-launch events on the same stream
-    binding.profile_begin(max_launches=4000 * max(1, args.steps))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        binding.nll_batch_raw(ds, theta, ws, out, stream=stream)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    kstats = binding.profile_end()
-
-    res = {k: v.cpu() for k, v in binding.unpack_results(out).items()}
-    n_ok = int((res["info"] == 0).sum())
+    mixed = None
+    if not args.no_mixed:
+        dtm, kstm, resm = timed("mixed_fast")
+    dt, kstats, res64 = timed("fp64")
+    if not args.no_mixed:
+        import numpy as np
+        sc = {"logdet": 1.0, "nll": 1.0, "mu": float(np.std(w.y)), "sigma2": 0.0}
+        errs = {k: float(np.max(np.abs(resm[k] - res64[k]) / np.maximum(np.abs(res64[k]), sc[k])))
+                for k in ("logdet", "mu", "sigma2", "nll")}
+        sym = kstm.get("syrk_update_f32", {"flops": 0.0, "ms": 1.0})
+        mixed = {"prec": "mixed_fast", "value": w.B * args.steps / dtm,
+                 "ms_per_step": dtm / args.steps * 1e3,
+                 "speedup_vs_fp64": dt / dtm,
+                 "max_rel_err_vs_fp64_gpu": errs,
+                 "results_ok": int((resm["info"] == 0).sum()),
+                 "trailing_update_tflops_fp32_mfma": sym["flops"] / (sym["ms"] * 1e-3) / 1e12,
+                 "matched_1e-8": bool(errs["nll"] <= 1e-8)}
+    n_ok = int((res64["info"] == 0).sum())
     evals = w.B * args.steps / dt
     ms_step = dt / args.steps * 1e3
 
@@ -124,6 +177,12 @@ def main():
         "results_ok": n_ok,
         "kernels": kernels,
     }
+    if mixed is not None:
+        line["mixed"] = mixed
+    if not args.no_serving:
+        del ws
+        torch.cuda.empty_cache()
+        line["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
         line["cpu_baseline"] = cpu_baseline(w, threads)

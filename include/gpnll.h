@@ -28,6 +28,9 @@
  *            strictly positive or was NaN; all outputs NaN
  *        -1  (y - 1 mu)' R^-1 (y - 1 mu) == 0 exactly: sigma2 = 0, nll = -inf
  *        -3  theta has a negative or non-finite entry; all outputs NaN
+ *        -2  (GP_MIXED_FAST) the refined solves did not reach an FP64-level
+ *            normwise backward error (1e-13); outputs are still returned
+ *        -4  (request server only) the micro-batch could not be launched
  *   - Matrices are column-major.  Internally the order is padded to
  *     n_pad = 64 * ceil(n / 64) with an identity block, which changes neither
  *     the determinant nor the solves.
@@ -55,7 +58,16 @@ typedef enum {
 } gp_status;
 
 typedef enum {
-    GP_FP64 = 0          /* every step in FP64 (FP64 MFMA for the trailing updates) */
+    GP_FP64 = 0,         /* every step in FP64 (FP64 MFMA for the trailing updates) */
+    GP_MIXED_FAST = 2    /* rank-256 trailing updates on FP32 MFMA with FP32
+                            accumulation; correlation build, diagonal
+                            factorisation, TRSM and log-det in FP64; the solves
+                            R x = [1 y] are refined with FP64 residuals (R
+                            regenerated from X) for 2 sweeps before mu and
+                            sigma2 are formed.  log|R| keeps the error of the
+                            factorisation; errors against the FP64 result are
+                            reported, not bounded (they grow with the
+                            conditioning of R). */
 } gp_prec;
 
 /* One result per theta (40 bytes). */
@@ -65,7 +77,7 @@ typedef struct {
     double sigma2;   /* eq. 3 */
     double nll;      /* log|R_delta| + n ln(sigma2)  (eq. 4 up to the constant n ln n) */
     int32_t info;    /* see the conventions above */
-    int32_t ir_iters;/* refinement sweeps taken (0 on the FP64 path) */
+    int32_t ir_iters;/* refinement sweeps (0 on the FP64 path) */
 } gp_result;
 
 /* A resident dataset.  X: device, n x d, row-major (x_i is row i).
@@ -122,6 +134,75 @@ size_t gp_cholesky_ws_bytes(int32_t n, int32_t batch);
 gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda,
                             int32_t *info, double *logdet, void *ws, size_t ws_bytes,
                             hipStream_t stream);
+
+/* Value and adjoint gradient of nll with respect to theta for `batch`
+ * thetas (FP64 only; prec must be GP_FP64):
+ *   d nll/d theta_k = tr(R^-1 dR/dtheta_k) - n r'R^-1 (dR/dtheta_k) R^-1 r / (r'R^-1 r),
+ *   r = y - 1 mu, dR_ij/dtheta_k = -R_ij |x_ik - x_jk|^p for i != j.
+ * (Sec. 2: gradient-based optimisers need this next to the likelihood.)
+ * R^-1 is obtained by carrying the blocked factorisation through the first
+ * n_pad columns of [[R, I], [I, 0]] (order 2 n_pad), which leaves -R^-1 in
+ * the bottom-right block.  out: device, batch results as gp_nll_batch;
+ * grad: device, batch x d row-major, NaN where info != 0.  ws: at least
+ * gp_grad_workspace_bytes(n, d, batch) bytes (four n_pad^2 doubles per
+ * theta), 16-byte aligned. */
+size_t gp_grad_workspace_bytes(int32_t n, int32_t d, int32_t batch);
+gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta,
+                      int32_t prec, void *ws, size_t ws_bytes, gp_result *out,
+                      double *grad, hipStream_t stream);
+
+/* ------------------------------------------------------------------------ */
+/* Continuous-batching request server (host API over gp_nll_batch).
+ * The paper evaluates one theta at a time and notes that evaluating the
+ * likelihood for many parameter values concurrently is the natural
+ * parallelism it could not use (Sec. 3); the server does that across
+ * requests that arrive over time, for several resident datasets of uneven n.
+ *
+ * gp_server_create: datasets (host array of descriptors whose X, y stay
+ *   resident on the device), an arena of caller-owned device memory (256-byte
+ *   aligned) from which every micro-batch's footprint is carved (admission by
+ *   HBM footprint), max_batch thetas per micro-batch, nstreams concurrent
+ *   micro-batches (streams of default priority), prec (GP_FP64 or
+ *   GP_MIXED_FAST).  Creates streams, events and pinned host staging.
+ * gp_server_submit: queues host requests (copied).  GP_EWORKSPACE if a
+ *   request could never fit the arena.
+ * gp_server_poll: non-blocking; retires finished micro-batches into `out`
+ *   (at most max_out completions; a batch is reported whole or not at all)
+ *   and launches queued work while a stream and arena space are free: the
+ *   oldest request picks the dataset, up to max_batch queued requests of it
+ *   (arrival order) form the batch, shrunk until it fits.  Returns the number
+ *   of completions written or a negative gp_status.  A result of a batch whose
+ *   launch failed has info = -4.
+ * gp_server_outstanding: requests queued or on the GPU.
+ * gp_server_destroy: waits for the streams, frees host resources.
+ * One host thread drives a server. */
+typedef struct gp_server gp_server;
+typedef struct {
+    int64_t id;
+    int32_t dataset;
+    int32_t pad_;
+    double theta[GP_DMAX];   /* first d entries used */
+} gp_request;
+typedef struct {
+    int64_t id;
+    int32_t dataset;
+    int32_t batch;           /* size of the micro-batch it ran in */
+    gp_result result;
+} gp_completion;
+typedef struct {
+    int32_t max_batch;
+    int32_t nstreams;
+    int32_t prec;
+    int32_t pad_;
+} gp_server_config;
+
+gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *arena,
+                           size_t arena_bytes, const gp_server_config *cfg, gp_server **out);
+gp_status gp_server_submit(gp_server *server, const gp_request *reqs, int32_t count);
+int32_t gp_server_poll(gp_server *server, gp_completion *out, int32_t max_out);
+int64_t gp_server_outstanding(const gp_server *server);
+size_t gp_server_arena_used(const gp_server *server);
+gp_status gp_server_destroy(gp_server *server);
 
 /* Per-launch timing for measurement.  gp_profile_begin(max_launches) makes
  * every later kernel launch of this library record two hipEvents on its own

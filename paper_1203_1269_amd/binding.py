@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(HERE, "libgpnll.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "gpnll.h")
 
 GP_OK, GP_EINVAL, GP_EWORKSPACE, GP_ELAUNCH = 0, -1, -2, -3
-PRECISIONS = {"fp64": 0}
+PRECISIONS = {"fp64": 0, "mixed_fast": 2}
 STATUS_NAMES = {0: "GP_OK", -1: "GP_EINVAL", -2: "GP_EWORKSPACE", -3: "GP_ELAUNCH"}
 
 
@@ -75,6 +75,10 @@ def lib():
         L.gp_cholesky_ws_bytes.restype = sz
         L.gp_cholesky_batch.argtypes = [i32, i32, vp, i32, vp, vp, vp, sz, vp]
         L.gp_cholesky_batch.restype = ctypes.c_int
+        L.gp_grad_workspace_bytes.argtypes = [i32, i32, i32]
+        L.gp_grad_workspace_bytes.restype = sz
+        L.gp_nll_grad.argtypes = [ctypes.POINTER(GPDataset), i32, vp, i32, vp, sz, vp, vp, vp]
+        L.gp_nll_grad.restype = ctypes.c_int
         L.gp_profile_begin.argtypes = [i32]
         L.gp_profile_begin.restype = ctypes.c_int
         L.gp_profile_end.argtypes = [ctypes.POINTER(GPKernelStat), i32]
@@ -218,3 +222,46 @@ def profile_end() -> dict:
     return {stats[q].name.decode(): {"launches": stats[q].launches, "ms": stats[q].ms,
                                      "flops": stats[q].flops, "bytes": stats[q].bytes}
             for q in range(m)}
+
+
+def grad_workspace_bytes(n: int, d: int, batch: int) -> int:
+    return int(lib().gp_grad_workspace_bytes(n, d, batch))
+
+
+def nll_grad(ds: Dataset, theta, ws: torch.Tensor | None = None):
+    """Profile likelihood and its adjoint gradient for each row of theta.
+    Returns (results dict as nll_batch, grad tensor B x d)."""
+    th = _dev_f64(theta, ds.device).reshape(-1, ds.d)
+    B = th.shape[0]
+    need = grad_workspace_bytes(ds.n, ds.d, B)
+    if need == 0:
+        raise GPError("gp_grad_workspace_bytes rejected the sizes")
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, ds.device)
+    out = torch.empty((B, 5), dtype=torch.float64, device=ds.device)
+    grad = torch.empty((B, ds.d), dtype=torch.float64, device=ds.device)
+    st = lib().gp_nll_grad(ds.c, B, ctypes.c_void_p(th.data_ptr()), PRECISIONS["fp64"],
+                           ctypes.c_void_p(ws.data_ptr()), ws.numel(), ctypes.c_void_p(out.data_ptr()),
+                           ctypes.c_void_p(grad.data_ptr()), _stream_ptr())
+    _check(st, "gp_nll_grad")
+    return unpack_results(out), grad
+
+
+class ProfileNLL(torch.autograd.Function):
+    """nll(theta) for a batch of thetas (B x d) with the adjoint gradient
+    computed by the library in the forward pass; backward scales it."""
+
+    @staticmethod
+    def forward(ctx, theta: torch.Tensor, ds: Dataset):
+        res, grad = nll_grad(ds, theta.detach())
+        ctx.save_for_backward(grad)
+        return res["nll"].clone()
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        (grad,) = ctx.saved_tensors
+        return grad_out[:, None] * grad, None
+
+
+def profile_nll(theta: torch.Tensor, ds: Dataset) -> torch.Tensor:
+    return ProfileNLL.apply(theta, ds)

@@ -297,6 +297,93 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
         }
 }
 
+// Trailing update with FP32 MFMA (v_mfma_f32_16x16x4f32) and FP32
+// accumulation, for the mixed-precision mode: the FP64 panel fragments are
+// rounded to FP32, the product sum over K is accumulated in FP32, and the
+// result is subtracted from the FP64 matrix in FP64.  Layout of the f32
+// MFMA (measured on gfx950): A[i][k] in lane i + 16k, B[k][j] in lane j + 16k,
+// D[i][j] in lane j + 16 (i / 4), element i % 4, so each lane's four
+// accumulator elements are four consecutive rows without permutation.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(SY_THREADS, 2)
+void syrk_update_f32_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int cs,
+                            int ce, int kc0, int K, int NR, int ntiles, int batch)
+{
+    const int W = ntiles * batch;
+    const int per = (W + NXCD - 1) / NXCD;
+    const int bid = blockIdx.x;
+    const int work = (bid % NXCD) * per + bid / NXCD;
+    if (work >= W) return;
+    const int b = work / ntiles;
+    int t = work - b * ntiles;
+    int jt = 0;
+    while (t >= NR - jt) { t -= NR - jt; ++jt; }
+    const int it = jt + t;
+
+    const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
+    const int r0 = cs + 128 * it + 64 * (wave >> 1);
+    const int c0 = cs + 128 * jt + 64 * (wave & 1);
+    if (r0 >= np || c0 >= ce || r0 < c0) return;   // no barriers below
+
+    double *A = A0 + (size_t)b * bstride;
+    const int li = lane & 15, lk = lane >> 4;
+    const double *pa = A + (size_t)(r0 + li) + (size_t)(kc0 + lk) * lda;
+    const double *pb = A + (size_t)(c0 + li) + (size_t)(kc0 + lk) * lda;
+    const size_t step4 = (size_t)4 * lda;
+    double a0[4], b0[4], a1[4], b1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
+
+    flt4 acc[4][4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) acc[rb][cb] = (flt4){0.f, 0.f, 0.f, 0.f};
+
+    for (int kk = 0; kk < K; kk += 8) {
+        float fa[4], fb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { fa[q] = (float)a0[q]; fb[q] = (float)b0[q]; }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[rb], fb[cb], acc[rb][cb], 0, 0, 0);
+        pa += 2 * step4;
+        pb += 2 * step4;
+        if (kk + 8 < K) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) { fa[q] = (float)a1[q]; fb[q] = (float)b1[q]; }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+            for (int cb = 0; cb < 4; ++cb)
+                acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[rb], fb[cb], acc[rb][cb], 0, 0, 0);
+        if (kk + 12 < K) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
+        }
+    }
+
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            double *p = A + (size_t)(r0 + 16 * rb + 4 * lk) + (size_t)(c0 + 16 * cb + li) * lda;
+            dbl2 lo = *(const dbl2 *)p;
+            dbl2 hi = *(const dbl2 *)(p + 2);
+            const flt4 v = acc[rb][cb];
+            *(dbl2 *)p = (dbl2){lo.x - (double)v.x, lo.y - (double)v.y};
+            *(dbl2 *)(p + 2) = (dbl2){hi.x - (double)v.z, hi.y - (double)v.w};
+        }
+}
+
 __global__ void logdet_sum_kernel(const double *__restrict__ lpart, int nparts, int batch,
                                   double *__restrict__ logdet)
 {
@@ -329,14 +416,16 @@ void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int b
 }
 
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce, int kc0,
-                        int K, int batch, hipStream_t s)
+                        int K, int batch, hipStream_t s, int prec)
 {
     if (ce <= cs || K <= 0) return;
     const double entries = (double)(ce - cs) * np - 0.5 * (double)(cs + ce - 1) * (ce - cs);
     // left-looking updates of one 64-column block inside an outer panel are
     // reported apart from the rank-256 trailing updates
     const bool block64 = (ce - cs) == TB;
-    ProfScope ps(block64 ? K_SYRK_PANEL : K_SYRK_UPDATE, 2.0 * K * entries * batch,
+    const bool f32 = !block64 && prec == GP_MIXED_FAST;
+    ProfScope ps(block64 ? K_SYRK_PANEL : (f32 ? K_SYRK_UPDATE_F32 : K_SYRK_UPDATE),
+                 2.0 * K * entries * batch,
                  (16.0 * entries + 8.0 * (double)(np - cs) * K) * batch, s);
     int NR, ntiles;
     if (block64) {
@@ -353,26 +442,37 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
     if (block64)
         syrk_update_kernel<4, 1><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
             A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
+    else if (f32)
+        syrk_update_f32_kernel<<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
     else
         syrk_update_kernel<2, 2><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
             A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
 }
 
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
-                  double *lpart, hipStream_t s)
+                  double *lpart, hipStream_t s, int prec, bool bordered)
 {
     const int nparts = np / TB;
     for (int c = 0; c < np; c += OUTER_NB) {
         const int pe = min(c + OUTER_NB, np);
         for (int c0 = c; c0 < pe; c0 += TB) {
+            // rows that can be nonzero in column block c0: with a border, row
+            // np + i is zero left of column i, so rows up to np + c0 + 63
+            const int rmax = bordered ? np + c0 + TB : np;
             // left-looking inside the outer panel: bring block c0 up to date
             // with the blocks [c, c0) of the same panel, then factor it
-            if (c0 > c) launch_syrk_update(A, lda, bstride, np, c0, c0 + TB, c, c0 - c, batch, s);
+            if (c0 > c)
+                launch_syrk_update(A, lda, bstride, rmax, c0, c0 + TB, c, c0 - c, batch, s, GP_FP64);
             launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, s);
-            launch_trsm_panel(A, lda, bstride, np, c0, batch, s);
+            launch_trsm_panel(A, lda, bstride, rmax, c0, batch, s);
         }
-        // right-looking rank-(pe - c) update of the trailing matrix
-        if (pe < np) launch_syrk_update(A, lda, bstride, np, pe, np, c, pe - c, batch, s);
+        // right-looking rank-(pe - c) update of the trailing matrix; with a
+        // border it also covers the border columns np .. np + pe - 1
+        if (bordered)
+            launch_syrk_update(A, lda, bstride, np + pe, pe, np + pe, c, pe - c, batch, s, prec);
+        else if (pe < np)
+            launch_syrk_update(A, lda, bstride, np, pe, np, c, pe - c, batch, s, prec);
     }
 }
 

@@ -14,16 +14,19 @@ constexpr size_t ALIGN = 256;
 
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
+constexpr int IR_SWEEPS = 2;   // refinement sweeps of the mixed mode
+
 struct Layout {
     int np;
     size_t mat;      // offset of the matrices
     size_t bstride;  // doubles per matrix
     size_t lpart;    // offset of the log-det partials
     size_t info;     // offset of info
+    size_t rhs, x, s; // refinement vectors (mixed mode), batch * 2 np doubles each
     size_t total;
 };
 
-bool layout_for(int n, int batch, Layout &L)
+bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
 {
     if (n < 2 || n > GP_NMAX || batch < 1) return false;
     L.np = pad64(n);
@@ -35,6 +38,14 @@ bool layout_for(int n, int batch, Layout &L)
     off = align_up(off + sizeof(double) * (size_t)(L.np / TB) * batch);
     L.info = off;
     off = align_up(off + sizeof(int32_t) * (size_t)batch);
+    L.rhs = L.x = L.s = off;
+    if (prec == GP_MIXED_FAST) {
+        const size_t vec = align_up(sizeof(double) * 2 * (size_t)L.np * batch);
+        L.rhs = off;
+        L.x = off + vec;
+        L.s = off + 2 * vec;
+        off += 3 * vec;
+    }
     L.total = off;
     return true;
 }
@@ -47,6 +58,8 @@ bool dataset_ok(const gp_dataset *ds)
     if (!(ds->delta >= 0.0) || !isfinite(ds->delta)) return false;
     return true;
 }
+
+bool prec_ok(int32_t prec) { return prec == GP_FP64 || prec == GP_MIXED_FAST; }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
@@ -62,19 +75,19 @@ extern "C" {
 size_t gp_workspace_bytes(int32_t n, int32_t d, int32_t batch, int32_t prec)
 {
     Layout L;
-    if (d < 1 || d > GP_DMAX || prec != GP_FP64) return 0;
-    if (!layout_for(n, batch, L)) return 0;
+    if (d < 1 || d > GP_DMAX || !prec_ok(prec)) return 0;
+    if (!layout_for(n, batch, L, prec)) return 0;
     return L.total;
 }
 
 gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
                        void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream)
 {
-    if (!dataset_ok(ds) || batch < 1 || !theta || !out || !ws || prec != GP_FP64)
+    if (!dataset_ok(ds) || batch < 1 || !theta || !out || !ws || !prec_ok(prec))
         return GP_EINVAL;
     if (!aligned16(ws)) return GP_EINVAL;
     Layout L;
-    if (!layout_for(ds->n, batch, L)) return GP_EINVAL;
+    if (!layout_for(ds->n, batch, L, prec)) return GP_EINVAL;
     if (ws_bytes < L.total) return GP_EWORKSPACE;
 
     char *base = (char *)ws;
@@ -86,9 +99,14 @@ gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta,
     launch_init(theta, ds->d, batch, info, stream);
     launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
                       stream);
-    factor_batch(A, np, L.bstride, np, batch, info, lpart, stream);
-    launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
-                        stream);
+    factor_batch(A, np, L.bstride, np, batch, info, lpart, stream, prec);
+    if (prec == GP_MIXED_FAST)
+        refine_solves(A, np, L.bstride, np, ds, theta, batch, lpart, info,
+                      (double *)(base + L.rhs), (double *)(base + L.x), (double *)(base + L.s),
+                      IR_SWEEPS, out, stream);
+    else
+        launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
+                            stream);
     return launched();
 }
 
@@ -126,8 +144,75 @@ gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda, in
     double *lpart = (double *)ws;
     const size_t bstride = (size_t)lda * lda;
     launch_pad_identity(A, lda, bstride, n, np, batch, stream);
-    factor_batch(A, lda, bstride, np, batch, info, lpart, stream);
+    factor_batch(A, lda, bstride, np, batch, info, lpart, stream, GP_FP64);
     launch_logdet_sum(lpart, np / TB, batch, logdet, stream);
+    return launched();
+}
+
+struct GradLayout {
+    int np, ntiles;
+    size_t lda, bstride, mat, lpart, info, alpha, part, total;
+};
+
+static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
+{
+    if (n < 2 || n > GP_NMAX || batch < 1 || d < 1 || d > GP_DMAX) return false;
+    L.np = pad64(n);
+    const int T = L.np / TB;
+    L.ntiles = T * (T + 1) / 2;
+    L.lda = (size_t)2 * L.np;
+    L.bstride = L.lda * L.lda;
+    size_t off = 0;
+    L.mat = off;
+    off = align_up(off + L.bstride * sizeof(double) * batch);
+    L.lpart = off;
+    off = align_up(off + sizeof(double) * (size_t)T * batch);
+    L.info = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)batch);
+    L.alpha = off;
+    off = align_up(off + sizeof(double) * (size_t)L.np * batch);
+    L.part = off;
+    off = align_up(off + sizeof(double) * (size_t)L.ntiles * d * batch);
+    L.total = off;
+    return true;
+}
+
+size_t gp_grad_workspace_bytes(int32_t n, int32_t d, int32_t batch)
+{
+    GradLayout L;
+    if (!grad_layout_for(n, d, batch, L)) return 0;
+    return L.total;
+}
+
+gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
+                      void *ws, size_t ws_bytes, gp_result *out, double *grad, hipStream_t stream)
+{
+    if (!dataset_ok(ds) || batch < 1 || !theta || !out || !grad || !ws || prec != GP_FP64)
+        return GP_EINVAL;
+    if (!aligned16(ws)) return GP_EINVAL;
+    GradLayout L;
+    if (!grad_layout_for(ds->n, ds->d, batch, L)) return GP_EINVAL;
+    if (ws_bytes < L.total) return GP_EWORKSPACE;
+
+    char *base = (char *)ws;
+    double *A = (double *)(base + L.mat);
+    double *lpart = (double *)(base + L.lpart);
+    int32_t *info = (int32_t *)(base + L.info);
+    double *alpha = (double *)(base + L.alpha);
+    double *part = (double *)(base + L.part);
+    const int np = L.np;
+    const int lda = (int)L.lda;
+
+    launch_init(theta, ds->d, batch, info, stream);
+    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, lda, L.bstride, np,
+                      stream);
+    launch_border_init(A, lda, L.bstride, np, batch, stream);
+    factor_batch(A, lda, L.bstride, np, batch, info, lpart, stream, GP_FP64, true);
+    launch_solve_reduce(A, lda, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
+                        stream);
+    launch_alpha(A, lda, L.bstride, np, ds->n, ds->y, out, alpha, batch, stream);
+    launch_adjoint(A, lda, L.bstride, np, ds->n, ds->d, ds->p, ds->X, theta, alpha, out, part,
+                   grad, batch, stream);
     return launched();
 }
 

@@ -38,12 +38,31 @@ void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int b
                        hipStream_t s);
 // C(r, c) -= sum_{k in [kc0, kc0+K)} A(r, k) A(c, k) for c in [cs, ce) and
 // r in [c's 128-tile row .. np), i.e. the lower part of the column range.
+// prec selects the arithmetic of rank-256 trailing updates (GP_FP64 or
+// GP_MIXED_FAST); updates of a single 64-column block are always FP64.
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce,
-                        int kc0, int K, int batch, hipStream_t s);
+                        int kc0, int K, int batch, hipStream_t s, int prec);
 
-// The whole blocked factorisation (a2) plus log-det partials (a3).
+// The whole blocked factorisation (a2) plus log-det partials (a3).  With
+// `bordered`, A has order 2 np and holds [[R, I], [I, 0]]; only the first np
+// columns are factored, which leaves L^-T bottom-left and -R^-1 bottom-right.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
-                  double *lpart, hipStream_t s);
+                  double *lpart, hipStream_t s, int prec, bool bordered = false);
+
+// a5: iterative refinement of R x = [1 y] with FP64 residuals (R regenerated
+// from X) and corrections through the factor A; then mu, sigma2, nll.
+// rhs, x, s: batch * 2 np doubles each.
+void refine_solves(const double *A, int lda, size_t bstride, int np, const gp_dataset *ds,
+                   const double *theta, int batch, const double *lpart, const int32_t *info,
+                   double *rhs, double *x, double *s, int sweeps, gp_result *out, hipStream_t st);
+
+// Gradient pieces (grad.hip).
+void launch_border_init(double *A, int lda, size_t bstride, int np, int batch, hipStream_t s);
+void launch_alpha(const double *A, int lda, size_t bstride, int np, int n, const double *y,
+                  const gp_result *res, double *alpha, int batch, hipStream_t s);
+void launch_adjoint(const double *A, int lda, size_t bstride, int np, int n, int d, double p,
+                    const double *X, const double *theta, const double *alpha,
+                    const gp_result *res, double *part, double *grad, int batch, hipStream_t s);
 
 // a3 alone: logdet[b] = sum of the nparts partials.
 void launch_logdet_sum(const double *lpart, int nparts, int batch, double *logdet,

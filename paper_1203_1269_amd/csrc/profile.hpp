@@ -14,9 +14,15 @@ enum KernelKind {
     K_TRSM_PANEL,
     K_SYRK_UPDATE,
     K_SYRK_PANEL,
+    K_SYRK_UPDATE_F32,
     K_SOLVE_REDUCE,
     K_PAD,
     K_LOGDET_SUM,
+    K_BORDER,
+    K_ALPHA,
+    K_ADJOINT,
+    K_RESIDUAL,
+    K_SOLVE2,
     K_NUM_KINDS
 };
 

@@ -1,0 +1,222 @@
+// Continuous-batching request server over resident datasets.
+//
+// Requests (dataset, theta) are queued on the host.  Each poll
+//   1. retires finished micro-batches (their completion event has fired):
+//      results are handed out, their arena block and stream are freed;
+//   2. admits queued work while a stream and arena space are free: the
+//      oldest queued request picks the dataset, up to max_batch queued
+//      requests of that dataset (in arrival order) form one micro-batch, its
+//      footprint (workspace + theta + results) is carved from the caller's
+//      arena, and the batch is launched on its own stream (theta upload,
+//      gp_nll_batch, result download, event).
+// Micro-batches of different datasets run concurrently on different streams,
+// so requests that arrive while others are on the GPU start as soon as a
+// stream and memory are free.  Every theta's arithmetic is independent of the
+// rest of its batch and of the other streams, so a request's result is
+// bitwise the one it gets alone.  Admission is strictly in arrival order of
+// the oldest request (no overtaking), so no request starves.
+#include <math.h>
+#include <string.h>
+
+#include <cmath>
+#include <deque>
+#include <vector>
+
+#include "arena.hpp"
+#include "kernels.hpp"
+
+using namespace gpk;
+
+struct gp_server {
+    std::vector<gp_dataset> ds;
+    char *arena_base = nullptr;
+    Arena arena;
+    int max_batch = 32;
+    int prec = GP_FP64;
+    std::deque<gp_request> pending;
+    struct Stream {
+        hipStream_t s = nullptr;
+        hipEvent_t done = nullptr;
+        double *h_theta = nullptr;      // pinned staging, max_batch * GP_DMAX
+        gp_result *h_out = nullptr;     // pinned results, max_batch
+        bool busy = false;
+        int dataset = -1, B = 0;
+        size_t off = 0, bytes = 0;
+        std::vector<int64_t> ids;
+    };
+    std::vector<Stream> streams;
+    int64_t in_flight = 0;
+};
+
+namespace {
+
+size_t batch_bytes(const gp_dataset &d, int B, int prec, size_t &ws_bytes, size_t &theta_off,
+                   size_t &out_off)
+{
+    ws_bytes = gp_workspace_bytes(d.n, d.d, B, prec);
+    if (ws_bytes == 0) return 0;
+    theta_off = Arena::round(ws_bytes);
+    out_off = theta_off + Arena::round(sizeof(double) * (size_t)B * d.d);
+    return out_off + Arena::round(sizeof(gp_result) * (size_t)B);
+}
+
+bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_request> &reqs)
+{
+    const gp_dataset &d = sv->ds[k];
+    const int B = (int)reqs.size();
+    size_t ws_bytes, theta_off, out_off;
+    const size_t need = batch_bytes(d, B, sv->prec, ws_bytes, theta_off, out_off);
+    size_t off;
+    if (need == 0 || !sv->arena.alloc(need, off)) return false;
+    char *base = sv->arena_base + off;
+    for (int q = 0; q < B; ++q)
+        memcpy(st.h_theta + (size_t)q * d.d, reqs[q].theta, sizeof(double) * d.d);
+    double *d_theta = (double *)(base + theta_off);
+    gp_result *d_out = (gp_result *)(base + out_off);
+    (void)hipMemcpyAsync(d_theta, st.h_theta, sizeof(double) * (size_t)B * d.d,
+                         hipMemcpyHostToDevice, st.s);
+    gp_status rc = gp_nll_batch(&d, B, d_theta, sv->prec, base, ws_bytes, d_out, st.s);
+    (void)hipMemcpyAsync(st.h_out, d_out, sizeof(gp_result) * B, hipMemcpyDeviceToHost, st.s);
+    (void)hipEventRecord(st.done, st.s);
+    st.busy = true;
+    st.dataset = k;
+    st.B = B;
+    st.off = off;
+    st.bytes = need;
+    st.ids.clear();
+    for (const gp_request &r : reqs) st.ids.push_back(r.id);
+    if (rc != GP_OK) {
+        // arguments were validated at submit; mark every result as failed
+        for (int q = 0; q < B; ++q) {
+            st.h_out[q].info = -4;
+            st.h_out[q].logdet = st.h_out[q].mu = st.h_out[q].sigma2 = st.h_out[q].nll = NAN;
+        }
+    }
+    return true;
+}
+
+}  // namespace
+
+extern "C" {
+
+gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *arena,
+                           size_t arena_bytes, const gp_server_config *cfg, gp_server **out)
+{
+    if (!datasets || ndatasets < 1 || !arena || !cfg || !out) return GP_EINVAL;
+    if (cfg->max_batch < 1 || cfg->max_batch > 1024 || cfg->nstreams < 1 || cfg->nstreams > 64)
+        return GP_EINVAL;
+    if (cfg->prec != GP_FP64 && cfg->prec != GP_MIXED_FAST) return GP_EINVAL;
+    if (((uintptr_t)arena & 255) != 0) return GP_EINVAL;
+    for (int k = 0; k < ndatasets; ++k) {
+        const gp_dataset &d = datasets[k];
+        if (!d.X || !d.y || d.n < 2 || d.n > GP_NMAX || d.d < 1 || d.d > GP_DMAX ||
+            !(d.p > 0.0 && d.p <= 2.0) || !(d.delta >= 0.0) || !std::isfinite(d.delta))
+            return GP_EINVAL;
+    }
+    gp_server *sv = new gp_server();
+    sv->ds.assign(datasets, datasets + ndatasets);
+    sv->arena_base = (char *)arena;
+    sv->arena.reset(arena_bytes);
+    sv->max_batch = cfg->max_batch;
+    sv->prec = cfg->prec;
+    sv->streams.resize(cfg->nstreams);
+    for (auto &st : sv->streams) {
+        bool ok = hipStreamCreateWithFlags(&st.s, hipStreamNonBlocking) == hipSuccess &&
+                  hipEventCreateWithFlags(&st.done, hipEventDisableTiming) == hipSuccess &&
+                  hipHostMalloc((void **)&st.h_theta, sizeof(double) * cfg->max_batch * GP_DMAX,
+                                hipHostMallocDefault) == hipSuccess &&
+                  hipHostMalloc((void **)&st.h_out, sizeof(gp_result) * cfg->max_batch,
+                                hipHostMallocDefault) == hipSuccess;
+        if (!ok) {
+            gp_server_destroy(sv);
+            return GP_ELAUNCH;
+        }
+    }
+    *out = sv;
+    return GP_OK;
+}
+
+gp_status gp_server_submit(gp_server *sv, const gp_request *reqs, int32_t count)
+{
+    if (!sv || (!reqs && count > 0) || count < 0) return GP_EINVAL;
+    for (int q = 0; q < count; ++q) {
+        const gp_request &r = reqs[q];
+        if (r.dataset < 0 || r.dataset >= (int)sv->ds.size()) return GP_EINVAL;
+        size_t a, b, c;
+        if (batch_bytes(sv->ds[r.dataset], 1, sv->prec, a, b, c) > sv->arena.size())
+            return GP_EWORKSPACE;   // would never fit
+    }
+    for (int q = 0; q < count; ++q) sv->pending.push_back(reqs[q]);
+    sv->in_flight += count;
+    return GP_OK;
+}
+
+int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
+{
+    if (!sv || max_out < 0 || (!out && max_out > 0)) return GP_EINVAL;
+    int32_t m = 0;
+    // 1. retire finished micro-batches
+    for (auto &st : sv->streams) {
+        if (!st.busy) continue;
+        if (m + st.B > max_out) continue;   // no room to report it yet
+        const hipError_t q = hipEventQuery(st.done);
+        if (q == hipErrorNotReady) continue;
+        for (int k = 0; k < st.B; ++k) {
+            out[m].id = st.ids[k];
+            out[m].dataset = st.dataset;
+            out[m].batch = st.B;
+            out[m].result = st.h_out[k];
+            if (q != hipSuccess) out[m].result.info = -4;
+            ++m;
+        }
+        sv->arena.release(st.off, st.bytes);
+        sv->in_flight -= st.B;
+        st.busy = false;
+    }
+    // 2. admit queued work, oldest first
+    for (auto &st : sv->streams) {
+        if (st.busy) continue;
+        if (sv->pending.empty()) break;
+        const int k = sv->pending.front().dataset;
+        std::vector<gp_request> batch;
+        std::vector<size_t> taken;
+        for (size_t q = 0; q < sv->pending.size() && (int)batch.size() < sv->max_batch; ++q)
+            if (sv->pending[q].dataset == k) {
+                batch.push_back(sv->pending[q]);
+                taken.push_back(q);
+            }
+        // shrink the batch until its footprint fits the free arena space
+        bool launched = false;
+        while (!batch.empty()) {
+            if (launch_batch(sv, st, k, batch)) {
+                launched = true;
+                break;
+            }
+            batch.pop_back();
+            taken.pop_back();
+        }
+        if (!launched) break;   // the oldest request waits for memory
+        for (size_t q = taken.size(); q-- > 0;) sv->pending.erase(sv->pending.begin() + (long)taken[q]);
+    }
+    return m;
+}
+
+int64_t gp_server_outstanding(const gp_server *sv) { return sv ? sv->in_flight : -1; }
+
+size_t gp_server_arena_used(const gp_server *sv) { return sv ? sv->arena.used() : 0; }
+
+gp_status gp_server_destroy(gp_server *sv)
+{
+    if (!sv) return GP_EINVAL;
+    for (auto &st : sv->streams) {
+        if (st.s) (void)hipStreamSynchronize(st.s);
+        if (st.done) (void)hipEventDestroy(st.done);
+        if (st.s) (void)hipStreamDestroy(st.s);
+        if (st.h_theta) (void)hipHostFree(st.h_theta);
+        if (st.h_out) (void)hipHostFree(st.h_out);
+    }
+    delete sv;
+    return GP_OK;
+}
+
+}  // extern "C"

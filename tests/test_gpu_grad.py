@@ -1,0 +1,145 @@
+"""Adjoint gradient on the GPU: against the 80-bit oracle gradient and
+against central differences of the GPU likelihood (h = 1e-6 theta_k)."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1203_1269_amd import inputs
+from parity_util import lapack_fp64, tolerances, to_host, compare
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def gp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1203_1269_amd import binding
+    binding.lib()
+    return binding
+
+
+def fd_gradient(gp, ds, th, h_rel=1e-6):
+    """Central differences, all perturbed thetas in one batched call."""
+    B, d = th.shape
+    pts = []
+    for t in range(B):
+        for k in range(d):
+            for sgn in (1.0, -1.0):
+                q = th[t].copy()
+                q[k] += sgn * h_rel * th[t, k]
+                pts.append(q)
+    res = to_host(gp.nll_batch(ds, np.array(pts)))
+    f = res["nll"].reshape(B, d, 2)
+    h = h_rel * th
+    return (f[:, :, 0] - f[:, :, 1]) / (2 * h)
+
+
+@pytest.mark.parametrize("n,d,p,delta", [(150, 3, 2.0, 1e-6), (257, 4, 1.95, 1e-6),
+                                         (300, 6, 2.0, 1e-4), (64, 2, 1.5, 1e-6),
+                                         (700, 5, 1.0, 1e-5)])
+def test_gradient_matches_oracle(gp, n, d, p, delta):
+    rng = np.random.default_rng(7000 + n)
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = inputs.log_uniform_theta(4, d, 0.2, 20, rng)
+    print(f"[grad] n={n} d={d} p={p}", flush=True)
+    ds = gp.Dataset(X, y, p, delta)
+    res, g = gp.nll_grad(ds, th)
+    torch.cuda.synchronize()
+    res, g = to_host(res), g.cpu().numpy()
+    # the value part of gp_nll_grad is the ordinary likelihood
+    r64 = oracle.nll_batch(X, y, th, p, delta)
+    r80 = oracle.nll_batch(X, y, th, p, delta, extended=True)
+    compare(res, r80, tolerances(r64, r80, y, lapack_fp64(X, y, th, p, delta)), y, "grad-values")
+    _, g64 = oracle.grad_batch(X, y, th, p, delta)
+    _, g80 = oracle.grad_batch(X, y, th, p, delta, extended=True)
+    scale = np.maximum(np.abs(g80), 1.0)
+    err = np.abs(g - g80) / scale
+    err64 = np.abs(g64 - g80) / scale
+    tol = np.maximum(1e-9, 20 * err64)
+    print("grad max rel err", err.max(), "oracle fp64 spread", err64.max())
+    assert np.all(err <= tol), (err, tol)
+
+
+def test_gradient_matches_finite_differences(gp):
+    rng = np.random.default_rng(7100)
+    n, d = 500, 6
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = inputs.log_uniform_theta(5, d, 0.5, 20, rng)
+    ds = gp.Dataset(X, y, 2.0, 1e-6)
+    _, g = gp.nll_grad(ds, th)
+    g = g.cpu().numpy()
+    fd = fd_gradient(gp, ds, th)
+    err = np.abs(g - fd) / np.maximum(np.abs(fd), 1.0)
+    print("fd max rel err", err.max())
+    assert np.all(err <= 1e-5), err
+
+
+def test_gradient_fullsize_against_finite_differences(gp):
+    """n=4096, d=6, p=2, nugget 1e-6, 16 thetas: adjoint vs central
+    differences of the GPU likelihood (h = 1e-6 theta_k)."""
+    w = inputs.gradient_workload()
+    print("[grad] fullsize n=4096 d=6 B=16", flush=True)
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    res, g = gp.nll_grad(ds, w.theta)
+    res, g = to_host(res), g.cpu().numpy()
+    assert np.all(res["info"] == 0)
+    fd = fd_gradient(gp, ds, w.theta)
+    err = np.abs(g - fd) / np.maximum(np.abs(fd), 1.0)
+    print("fullsize fd max rel err", err.max())
+    assert np.all(err <= 1e-5), err
+    # the value part equals the plain likelihood path bitwise in log|R|
+    plain = to_host(gp.nll_batch(ds, w.theta))
+    assert np.allclose(plain["nll"], res["nll"], rtol=1e-12, atol=0)
+
+
+def test_autograd_function(gp):
+    rng = np.random.default_rng(7200)
+    n, d = 200, 3
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = torch.tensor(inputs.log_uniform_theta(3, d, 0.5, 10, rng), device="cuda",
+                      requires_grad=True)
+    ds = gp.Dataset(X, y, 2.0, 1e-6)
+    f = gp.profile_nll(th, ds)
+    w = torch.tensor([1.0, -2.0, 0.5], device="cuda", dtype=torch.float64)
+    (f * w).sum().backward()
+    _, g = gp.nll_grad(ds, th.detach())
+    assert torch.allclose(th.grad, w[:, None] * g, rtol=0, atol=0)
+
+
+def test_gradient_failed_theta_is_nan(gp):
+    X = np.random.default_rng(7300).random((80, 2))
+    ds = gp.Dataset(X, np.arange(80.0), 2.0, 0.0)
+    res, g = gp.nll_grad(ds, np.array([[50.0, 60.0], [0.0, 0.0], [-1.0, 1.0]]))
+    res, g = to_host(res), g.cpu().numpy()
+    assert list(res["info"]) == [0, 2, -3]
+    assert np.all(np.isfinite(g[0])) and np.all(np.isnan(g[1:]))
+
+
+def test_lbfgs_multistart_descends_and_matches_scipy(gp):
+    """Batched L-BFGS in log(theta): monotone descent for every start, and the
+    final value agrees with SciPy's L-BFGS-B driven by the CPU oracle from the
+    same starting points."""
+    import scipy.optimize as so
+    from paper_1203_1269_amd import optim
+    rng = np.random.default_rng(7400)
+    n, d = 240, 2
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th0 = inputs.log_uniform_theta(3, d, 0.5, 5.0, rng)
+    ds = gp.Dataset(X, y, 2.0, 1e-6)
+    fit = optim.lbfgs_multistart(ds, th0, iters=40)
+    assert all(b <= a + 1e-9 * abs(a) for a, b in zip(fit.history, fit.history[1:]))
+    for s in range(3):
+        def fg(phi):
+            th = np.exp(phi)[None]
+            r, g = oracle.grad_batch(X, y, th, 2.0, 1e-6)
+            return float(r.nll[0]), g[0] * np.exp(phi)
+        ref = so.minimize(fg, np.log(th0[s]), jac=True, method="L-BFGS-B",
+                          options={"maxiter": 200, "gtol": 1e-10, "ftol": 1e-15})
+        print("start", s, "gpu", fit.nll[s], "scipy", ref.fun)
+        assert fit.nll[s] <= ref.fun + 1e-7 * abs(ref.fun)

@@ -258,3 +258,52 @@ def test_fullsize_fp64_n4096_d8_sampled(gp):
     # properties at every theta: Hadamard bound, finite outputs, sigma2 > 0
     assert np.all(got["logdet"] <= w.n * math.log1p(w.delta) + 1e-9)
     assert np.all(got["sigma2"] > 0) and np.all(np.isfinite(got["nll"]))
+
+
+# ---------------------------------------------------------------------------
+# Mixed precision (FP32-MFMA trailing updates): errors are reported against
+# the oracle; they are bounded only loosely because they scale with the
+# conditioning of R.
+
+def test_mixed_fast_single_panel_factor_is_fp64(gp):
+    """Without a rank-256 trailing update (n <= 256) the mixed mode factors
+    with the FP64 kernels only: log|R| is bitwise the FP64 one, and the
+    refined mu and sigma2 stay within the FP64 tolerance."""
+    w = inputs.small_2d()
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    a = to_host(gp.nll_batch(ds, w.theta, prec="fp64"))
+    b = to_host(gp.nll_batch(ds, w.theta, prec="mixed_fast"))
+    assert np.array_equal(a["logdet"], b["logdet"])
+    r64 = oracle.nll_batch(w.X, w.y, w.theta, w.p, w.delta)
+    r80 = oracle.nll_batch(w.X, w.y, w.theta, w.p, w.delta, extended=True)
+    tol = tolerances(r64, r80, w.y, lapack_fp64(w.X, w.y, w.theta, w.p, w.delta))
+    sc = scales(w.y)
+    for k in ("mu", "sigma2", "nll"):
+        e = oracle.rel(b[k], getattr(r80, k), sc[k])
+        assert np.all(e <= 100 * tol[k]), (k, e.max())
+
+
+@pytest.mark.parametrize("n,d,p", [(1500, 8, 1.95), (2048, 6, 2.0)])
+def test_mixed_fast_errors_reported(gp, n, d, p):
+    rng = np.random.default_rng(6000 + n)
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = inputs.log_uniform_theta(6, d, 0.05, 20, rng)
+    print(f"[parity] mixed_fast n={n} d={d}", flush=True)
+    ds = gp.Dataset(X, y, p, 1e-6)
+    got = to_host(gp.nll_batch(ds, th, prec="mixed_fast"))
+    r80 = oracle.nll_batch(X, y, th, p, 1e-6, extended=True)
+    assert np.all(np.isin(got["info"], [0, -2])) and np.all(r80.info == 0)
+    sc = scales(y)
+    errs = {k: oracle.rel(got[k], getattr(r80, k), sc[k]) for k in ("logdet", "mu", "sigma2", "nll")}
+    print("mixed_fast max rel err vs 80-bit oracle:", {k: float(v.max()) for k, v in errs.items()},
+          "refinement sweeps", got["ir_iters"], "info", got["info"])
+    for k in ("logdet", "nll"):
+        assert np.all(errs[k] <= 1e-3), (k, errs[k])
+    # the refined solves bring mu and sigma2 to the FP64 level (the FP64
+    # rounding spread of the oracle and LAPACK, with a wider multiple)
+    r64 = oracle.nll_batch(X, y, th, p, 1e-6)
+    tol = tolerances(r64, r80, y, lapack_fp64(X, y, th, p, 1e-6))
+    for k in ("mu", "sigma2"):
+        assert np.all(errs[k] <= 100 * tol[k]), (k, errs[k], tol[k])
+    assert np.all(got["ir_iters"] == 2)
