@@ -27,6 +27,23 @@ if ROOT not in sys.path:
 METRIC = "-2logL evals/sec at n=4096,d=8 (mixed vs FP64 GPU); p50/p99 request latency"
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
+SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
+
+# HBM traffic of the rank-256 trailing update (syrk_update_kernel) on this
+# workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
+# what the same counters read for a 512 MiB device copy (bench.py
+# --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).
+# Valid only for the kernel text it was taken on: reported as null once the
+# sha256 of that kernel's source differs.
+SYRK_TRAFFIC = {"kernel_sha256": "5d1ce42c1d506d4f0d69b2aa52d1066c54f5538fb69f4b8dd62f218c2a93cfa8",
+                "bytes_per_launch": (2.0 * 4.36e7 + 1.0 * 4.162e7) / 15 * 1024}
+
+
+def syrk_kernel_text():
+    with open(SYRK_SRC) as f:
+        src = f.read()
+    i = src.index("void syrk_update_kernel(")
+    return src[i:src.index("\n}\n", i) + 3]
 
 
 def parse():
@@ -39,8 +56,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
+    ap.add_argument("--no-large", action="store_true", help="skip the n=8192 leg")
+    ap.add_argument("--no-grad", action="store_true", help="skip the gradient / L-BFGS leg")
     ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--serving-arena-gb", type=float, default=16.0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 512 MiB device-to-device copy first (counter calibration)")
     ap.add_argument("--cpu-threads", type=int, default=0,
                     help="oracle threads (default: min(16, available cores))")
     return ap.parse_args()
@@ -59,6 +80,14 @@ def cpu_baseline(w, threads):
     return {"value": len(th) / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(th)} of the {w.B} thetas of the same n={w.n}, d={w.d} workload, "
                       f"one theta per thread, {dt:.1f} s wall"}
+
+
+def syrk_traffic():
+    import hashlib
+    h = hashlib.sha256(syrk_kernel_text().encode()).hexdigest()
+    if SYRK_TRAFFIC["kernel_sha256"] != h:
+        return None
+    return SYRK_TRAFFIC["bytes_per_launch"]
 
 
 def serving_leg(args, dev):
@@ -92,6 +121,113 @@ def serving_leg(args, dev):
     return out
 
 
+PRECS = ("fp64", "mixed", "mixed_fast")
+
+
+def time_batch(binding, torch, ds, theta, ws, prec, steps, warmup, profile=True):
+    """`warmup` untimed then `steps` timed gp_nll_batch calls on the current
+    stream; returns (seconds, per-kernel stats of the timed calls, results)."""
+    B = theta.shape[0]
+    out = torch.empty((B, 5), dtype=torch.float64, device=theta.device)
+    stream = torch.cuda.current_stream()
+    for _ in range(warmup):
+        binding.nll_batch_raw(ds, theta, ws, out, prec=prec, stream=stream)
+    torch.cuda.synchronize()
+    if profile:   # the library records per-launch events on the same stream
+        binding.profile_begin(max_launches=4000 * max(1, steps))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        binding.nll_batch_raw(ds, theta, ws, out, prec=prec, stream=stream)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    kstats = binding.profile_end() if profile else {}
+    res = {k: v.cpu().numpy().copy() for k, v in binding.unpack_results(out).items()}
+    return dt, kstats, res
+
+
+def rel_errs(res, ref, y):
+    import numpy as np
+    sc = {"logdet": 1.0, "nll": 1.0, "mu": float(np.std(y)), "sigma2": 0.0}
+    ok = (res["info"] == 0) & (ref["info"] == 0)
+    if not ok.any():
+        return {k: None for k in sc}, ok
+    return {k: float(np.max(np.abs(res[k][ok] - ref[k][ok]) /
+                            np.maximum(np.abs(ref[k][ok]), sc[k]))) for k in sc}, ok
+
+
+def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps):
+    errs, ok = rel_errs(res, res64, w.y)
+    out = {"prec": prec, "value": w.B * steps / dt, "ms_per_step": dt / steps * 1e3,
+           "speedup_vs_fp64": dt64 / dt, "max_rel_err_vs_fp64_gpu": errs,
+           "results_ok": int((res["info"] == 0).sum()),
+           "results_recomputed_fp64": int((res["ir_iters"] == -1).sum()),
+           "matched_1e-8": bool(errs["nll"] is not None and errs["nll"] <= 1e-8 and ok.all()),
+           "kernels_ms_per_step": {k: v["ms"] / steps for k, v in kst.items()}}
+    if prec == "mixed":
+        sy = kst.get("syrk_update_i8", {"flops": 0.0, "ms": 1.0})
+        out["trailing_update_fp64_equiv_tflops"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+        # INT8 MFMA operations actually issued: 28 digit pairs per FP64 product
+        out["trailing_update_int8_tops"] = 28 * sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+    else:
+        sy = kst.get("syrk_update_f32", {"flops": 0.0, "ms": 1.0})
+        out["trailing_update_tflops_fp32_mfma"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+    return out
+
+
+def large_leg(args, dev):
+    """n=8192, d=10, p=2, 32 thetas: FP64 and matched-accuracy mixed."""
+    import torch
+    from paper_1203_1269_amd import binding, inputs
+    w = inputs.mixed_at_scale()
+    ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
+    theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
+    ws = binding.alloc_workspace(max(binding.workspace_bytes(w.n, w.d, w.B, p) for p in
+                                     ("fp64", "mixed")), dev)
+    steps = max(1, args.steps // 3)
+    dt64, k64, r64 = time_batch(binding, torch, ds, theta, ws, "fp64", steps, 1)
+    dtm, km, rm = time_batch(binding, torch, ds, theta, ws, "mixed", steps, 1)
+    del ws
+    torch.cuda.empty_cache()
+    sy = k64["syrk_update"]
+    return {"workload": w.name, "n": w.n, "d": w.d, "batch": w.B, "p": w.p, "delta": w.delta,
+            "steps": steps, "fp64_evals_per_s": w.B * steps / dt64,
+            "fp64_syrk_update_frac_of_peak": sy["flops"] / (sy["ms"] * 1e-3) / FP64_MFMA_PEAK,
+            "fp64_factorization_frac_of_peak": w.n ** 3 / 3.0 * w.B * steps / dt64 / FP64_MFMA_PEAK,
+            "fp64_results_ok": int((r64["info"] == 0).sum()),
+            "mixed": mixed_summary("mixed", dtm, km, rm, dt64, r64, w, steps)}
+
+
+def gradient_leg(args, dev):
+    """n=4096, d=6, p=2, 16 thetas: value + adjoint gradient per call
+    (bordered factorisation), and 16 multi-start L-BFGS fits x 50 iterations."""
+    import numpy as np
+    import torch
+    from paper_1203_1269_amd import binding, inputs, optim
+    w = inputs.gradient_workload()
+    ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
+    theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
+    ws = binding.alloc_workspace(binding.grad_workspace_bytes(w.n, w.d, w.B), dev)
+    binding.nll_grad(ds, theta, ws)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, g = binding.nll_grad(ds, theta, ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    del ws
+    torch.cuda.empty_cache()
+    t1 = time.perf_counter()
+    fit = optim.lbfgs_multistart(ds, w.theta, iters=50)
+    torch.cuda.synchronize()
+    dfit = time.perf_counter() - t1
+    return {"workload": w.name, "n": w.n, "d": w.d, "batch": w.B,
+            "value_and_grad_per_s": w.B * steps / dt, "ms_per_call": dt / steps * 1e3,
+            "lbfgs_starts": int(w.B), "lbfgs_iters_max": 50, "lbfgs_seconds": dfit,
+            "lbfgs_batched_calls": int(fit.evaluations), "lbfgs_best_nll": float(np.min(fit.nll))}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -104,46 +240,24 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(1 << 26, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     w = inputs.fp64_at_scale(n=args.n, B=args.batch)
     ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
     theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
-    ws = binding.alloc_workspace(binding.workspace_bytes(w.n, w.d, w.B), dev)
-    out = torch.empty((w.B, 5), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
+    precs = ("fp64",) if args.no_mixed else PRECS
+    ws = binding.alloc_workspace(max(binding.workspace_bytes(w.n, w.d, w.B, p) for p in precs), dev)
 
-    def timed(prec):
-        for _ in range(args.warmup):
-            binding.nll_batch_raw(ds, theta, ws, out, prec=prec, stream=stream)
-        torch.cuda.synchronize()
-        # timed region; the library records per-launch events on the same stream
-        binding.profile_begin(max_launches=4000 * max(1, args.steps))
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            binding.nll_batch_raw(ds, theta, ws, out, prec=prec, stream=stream)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        kstats = binding.profile_end()
-        res = {k: v.cpu().numpy().copy() for k, v in binding.unpack_results(out).items()}
-        return dt, kstats, res
+    runs = {}
+    for prec in reversed(precs):   # FP64 last: its line is the one profiled alone
+        runs[prec] = time_batch(binding, torch, ds, theta, ws, prec, args.steps, args.warmup)
+    dt, kstats, res64 = runs["fp64"]
+    mixed = {p: mixed_summary(p, *runs[p], dt, res64, w, args.steps) for p in precs if p != "fp64"}
 
-    mixed = None
-    if not args.no_mixed:
-        dtm, kstm, resm = timed("mixed_fast")
-    dt, kstats, res64 = timed("fp64")
-    if not args.no_mixed:
-        import numpy as np
-        sc = {"logdet": 1.0, "nll": 1.0, "mu": float(np.std(w.y)), "sigma2": 0.0}
-        errs = {k: float(np.max(np.abs(resm[k] - res64[k]) / np.maximum(np.abs(res64[k]), sc[k])))
-                for k in ("logdet", "mu", "sigma2", "nll")}
-        sym = kstm.get("syrk_update_f32", {"flops": 0.0, "ms": 1.0})
-        mixed = {"prec": "mixed_fast", "value": w.B * args.steps / dtm,
-                 "ms_per_step": dtm / args.steps * 1e3,
-                 "speedup_vs_fp64": dt / dtm,
-                 "max_rel_err_vs_fp64_gpu": errs,
-                 "results_ok": int((resm["info"] == 0).sum()),
-                 "trailing_update_tflops_fp32_mfma": sym["flops"] / (sym["ms"] * 1e-3) / 1e12,
-                 "matched_1e-8": bool(errs["nll"] <= 1e-8)}
     n_ok = int((res64["info"] == 0).sum())
     evals = w.B * args.steps / dt
     ms_step = dt / args.steps * 1e3
@@ -172,16 +286,20 @@ def main():
                    "delta": w.delta, "prec": "fp64", "seed": w.seed},
         "roofline": {"bound": "mfma", "kernel": "syrk_update", "achieved": achieved / 1e12,
                      "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
-                     "frac": achieved / FP64_MFMA_PEAK, "traffic": None},
+                     "frac": achieved / FP64_MFMA_PEAK, "traffic": syrk_traffic(),
+                     "traffic_unit": "bytes per launch"},
         "factorization_frac_of_fp64_peak": factor_flops * evals / FP64_MFMA_PEAK,
         "results_ok": n_ok,
         "kernels": kernels,
     }
-    if mixed is not None:
-        line["mixed"] = mixed
+    line.update(mixed)
+    del ws
+    torch.cuda.empty_cache()
+    if not args.no_large:
+        line["large_n8192"] = large_leg(args, dev)
+    if not args.no_grad:
+        line["gradient"] = gradient_leg(args, dev)
     if not args.no_serving:
-        del ws
-        torch.cuda.empty_cache()
         line["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))

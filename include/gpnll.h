@@ -28,8 +28,6 @@
  *            strictly positive or was NaN; all outputs NaN
  *        -1  (y - 1 mu)' R^-1 (y - 1 mu) == 0 exactly: sigma2 = 0, nll = -inf
  *        -3  theta has a negative or non-finite entry; all outputs NaN
- *        -2  (GP_MIXED_FAST) the refined solves did not reach an FP64-level
- *            normwise backward error (1e-13); outputs are still returned
  *        -4  (request server only) the micro-batch could not be launched
  *   - Matrices are column-major.  Internally the order is padded to
  *     n_pad = 64 * ceil(n / 64) with an identity block, which changes neither
@@ -59,6 +57,18 @@ typedef enum {
 
 typedef enum {
     GP_FP64 = 0,         /* every step in FP64 (FP64 MFMA for the trailing updates) */
+    GP_MIXED = 1,        /* matched accuracy: the rank-256 trailing updates
+                            C -= P P^T run on INT8 MFMA through an error-free
+                            splitting of P (per-row power-of-two scale, 7
+                            signed 7-bit digits, the 28 digit pairs of
+                            combined weight >= 2^-63 accumulated exactly in
+                            INT32 and combined in FP64); every other step in
+                            FP64.  About 49 significant bits per update
+                            relative to the row scales: -2logL agrees with
+                            the FP64 path well within 1e-8 relative.  A theta
+                            whose factorisation loses positive definiteness
+                            is recomputed on the FP64 path within the same
+                            call (gp_result.ir_iters = -1). */
     GP_MIXED_FAST = 2    /* rank-256 trailing updates on FP32 MFMA with FP32
                             accumulation; correlation build, diagonal
                             factorisation, TRSM and log-det in FP64; the solves
@@ -67,7 +77,11 @@ typedef enum {
                             sigma2 are formed.  log|R| keeps the error of the
                             factorisation; errors against the FP64 result are
                             reported, not bounded (they grow with the
-                            conditioning of R). */
+                            conditioning of R).  A theta whose mixed
+                            factorisation loses positive definiteness or
+                            whose refinement stays above the FP64 backward
+                            error is recomputed on the FP64 path within the
+                            same call (gp_result.ir_iters = -1). */
 } gp_prec;
 
 /* One result per theta (40 bytes). */
@@ -77,7 +91,8 @@ typedef struct {
     double sigma2;   /* eq. 3 */
     double nll;      /* log|R_delta| + n ln(sigma2)  (eq. 4 up to the constant n ln n) */
     int32_t info;    /* see the conventions above */
-    int32_t ir_iters;/* refinement sweeps (0 on the FP64 path) */
+    int32_t ir_iters;/* refinement sweeps (0 on the FP64 and GP_MIXED paths;
+                        -1 when a mixed theta was recomputed in FP64) */
 } gp_result;
 
 /* A resident dataset.  X: device, n x d, row-major (x_i is row i).
@@ -162,7 +177,7 @@ gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta,
  *   resident on the device), an arena of caller-owned device memory (256-byte
  *   aligned) from which every micro-batch's footprint is carved (admission by
  *   HBM footprint), max_batch thetas per micro-batch, nstreams concurrent
- *   micro-batches (streams of default priority), prec (GP_FP64 or
+ *   micro-batches (streams of default priority), prec (GP_FP64, GP_MIXED or
  *   GP_MIXED_FAST).  Creates streams, events and pinned host staging.
  * gp_server_submit: queues host requests (copied).  GP_EWORKSPACE if a
  *   request could never fit the arena.

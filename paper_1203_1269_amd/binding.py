@@ -14,11 +14,11 @@ import re
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libgpnll.so")
+LIB_PATH = os.environ.get("GPNLL_LIB") or os.path.join(HERE, "libgpnll.so")
 HEADER = os.path.join(os.path.dirname(HERE), "include", "gpnll.h")
 
 GP_OK, GP_EINVAL, GP_EWORKSPACE, GP_ELAUNCH = 0, -1, -2, -3
-PRECISIONS = {"fp64": 0, "mixed_fast": 2}
+PRECISIONS = {"fp64": 0, "mixed": 1, "mixed_fast": 2}
 STATUS_NAMES = {0: "GP_OK", -1: "GP_EINVAL", -2: "GP_EWORKSPACE", -3: "GP_ELAUNCH"}
 
 

@@ -57,8 +57,10 @@ constexpr int PO_THREADS = 256;
 
 __global__ __launch_bounds__(PO_THREADS)
 void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
-                       int32_t *__restrict__ info, double *__restrict__ lpart, int nparts)
+                       int32_t *__restrict__ info, double *__restrict__ lpart, int nparts,
+                       double *__restrict__ lk0, const uint8_t *__restrict__ mask)
 {
+    if (mask && !mask[blockIdx.x]) return;   // uniform over the workgroup
     __shared__ double col[2][TB];
     __shared__ double dg[TB];
     const int b = blockIdx.x;
@@ -90,10 +92,15 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
             if (m > mj || q > qj) a[m] = fma(-lrj, cb[c] * linv, a[m]);
         }
     }
+    // the factor, and a copy for the TRSM of this step: column-major,
+    // strict upper triangle zero, diagonal replaced by 1 / L_jj
+    double *lk = lk0 + (size_t)b * TB * TB;
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
         const int c = q + 4 * m;
-        A[(size_t)r + (size_t)c * lda] = (r >= c) ? a[m] : 0.0;
+        const double v = (r >= c) ? a[m] : 0.0;
+        A[(size_t)r + (size_t)c * lda] = v;
+        lk[(size_t)c * TB + r] = (r == c) ? 1.0 / v : v;
     }
     __syncthreads();
     if (tid < TB) {
@@ -109,80 +116,48 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
 
 // ---------------------------------------------------------------------------
 // TRSM: rows below the diagonal tile, X L_kk' = A, i.e. per row
-// x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj, right-looking over j.
-// 4 lanes per row group (lane q holds columns q, q+4, ..., q+60); each lane
-// group holds TR_RPL rows (every L value read from LDS feeds TR_RPL FMAs).  The solved x_j is passed to the other lanes of the group by a
-// DPP quad broadcast; L_kk sits in LDS permuted so that the values a lane
-// needs for one j are contiguous.
+// x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj, right-looking over j.  One lane
+// per row with its 64 entries in registers.  L_kk is read from the
+// read-only copy written by potrf_diag: every lane of a wave needs the same
+// L value at the same time, so the reads are scalar loads into SGPRs and each
+// FP64 FMA takes its L operand from an SGPR (no LDS traffic).  The diagonal
+// of the copy holds 1 / L_jj.
 
 constexpr int TR_THREADS = 256;
-constexpr int TR_RPL = 1;
-constexpr int TR_ROWS = TR_THREADS / 4 * TR_RPL;
+constexpr int TR_ROWS = TR_THREADS;
+#ifndef TR_MIN_BLOCKS
+#define TR_MIN_BLOCKS 3
+#endif
 
-__global__ __launch_bounds__(TR_THREADS)
-void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int c0)
+__global__ __launch_bounds__(TR_THREADS, TR_MIN_BLOCKS)
+void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int c0,
+                       const double *__restrict__ lk0, const uint8_t *__restrict__ mask)
 {
-    __shared__ double Lp[TB][4][16];   // Lp[j][q][m] = L(q + 4m, j)
-    __shared__ double rinv[TB];
     const int b = blockIdx.y;
-    const int tid = threadIdx.x;
+    if (mask && !mask[b]) return;
     double *A = A0 + (size_t)b * bstride;
+    const double *lk = lk0 + (size_t)b * TB * TB;
+    const int row = c0 + TB + blockIdx.x * TR_ROWS + threadIdx.x;
+    if (row >= np) return;
+    double x[TB];
     {
-        // all 16 loads in flight before the LDS stores
-        double t[TB * TB / TR_THREADS];
+        const double *p = A + (size_t)row + (size_t)c0 * lda;
 #pragma unroll
-        for (int k = 0; k < TB * TB / TR_THREADS; ++k) {
-            const int e = tid + k * TR_THREADS, rr = e % TB, c = e / TB;
-            t[k] = A[(size_t)(c0 + rr) + (size_t)(c0 + c) * lda];
-        }
-#pragma unroll
-        for (int k = 0; k < TB * TB / TR_THREADS; ++k) {
-            const int e = tid + k * TR_THREADS, rr = e % TB, c = e / TB;
-            Lp[c][rr & 3][rr >> 2] = t[k];
-        }
-    }
-    __syncthreads();
-    if (tid < TB) rinv[tid] = 1.0 / Lp[tid][tid & 3][tid >> 2];
-    __syncthreads();
-    const int q = tid & 3;
-    // rows base + g + 64 i, i < TR_RPL; np and base are multiples of 64, so
-    // each i is valid or invalid for the whole workgroup
-    const int base = c0 + TB + blockIdx.x * TR_ROWS + (tid >> 2);
-    double x[TR_RPL][16];
-    double *p[TR_RPL];
-#pragma unroll
-    for (int i = 0; i < TR_RPL; ++i) {
-        const int row = base + 64 * i;
-        p[i] = A + (size_t)min(row, np - 1) + (size_t)(c0 + q) * lda;
-#pragma unroll
-        for (int m = 0; m < 16; ++m) x[i][m] = (row < np) ? p[i][(size_t)(4 * m) * lda] : 0.0;
+        for (int c = 0; c < TB; ++c) { x[c] = *p; p += lda; }
     }
 #pragma unroll
     for (int j = 0; j < TB; ++j) {
-        const int qj = j & 3, mj = j >> 2;
-        const double rj = rinv[j];
-        double xj[TR_RPL];
+        x[j] = x[j] * lk[j * TB + j];
 #pragma unroll
-        for (int i = 0; i < TR_RPL; ++i) {
-            xj[i] = quad_bcast(x[i][mj] * rj, qj);
-            if (q == qj) x[i][mj] = xj[i];
-        }
-#pragma unroll
-        for (int m = mj; m < 16; ++m) {
-            const double l = Lp[j][q][m];
-            if (m > mj || q > qj) {
-#pragma unroll
-                for (int i = 0; i < TR_RPL; ++i) x[i][m] = fma(-xj[i], l, x[i][m]);
-            }
-        }
+        for (int c = j + 1; c < TB; ++c) x[c] = fma(-x[j], lk[j * TB + c], x[c]);
     }
+    // recompute the store addresses rather than keeping 64 of them live, so
+    // that two waves fit per SIMD (the scalar-load latency is then hidden)
+    int r2 = row;
+    asm volatile("" : "+v"(r2));
+    double *q = A + (size_t)r2 + (size_t)c0 * lda;
 #pragma unroll
-    for (int i = 0; i < TR_RPL; ++i) {
-        if (base + 64 * i < np) {
-#pragma unroll
-            for (int m = 0; m < 16; ++m) p[i][(size_t)(4 * m) * lda] = x[i][m];
-        }
-    }
+    for (int c = 0; c < TB; ++c) { *q = x[c]; q += lda; }
 }
 
 // ---------------------------------------------------------------------------
@@ -212,7 +187,8 @@ constexpr int NXCD = 8;
 template <int WR, int WC>
 __global__ __launch_bounds__(SY_THREADS, 2)
 void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int cs,
-                        int ce, int kc0, int K, int NR, int ntiles, int batch)
+                        int ce, int kc0, int K, int NR, int ntiles, int batch,
+                        const uint8_t *__restrict__ mask)
 {
     constexpr int TR = 64 * WR, TC = 64 * WC;
     const int W = ntiles * batch;
@@ -221,6 +197,7 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
     const int work = (bid % NXCD) * per + bid / NXCD;
     if (work >= W) return;
     const int b = work / ntiles;
+    if (mask && !mask[b]) return;
     int t = work - b * ntiles;
     int jt = 0, it = t;
     if (WC > 1) {
@@ -308,7 +285,8 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(SY_THREADS, 2)
 void syrk_update_f32_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int cs,
-                            int ce, int kc0, int K, int NR, int ntiles, int batch)
+                            int ce, int kc0, int K, int NR, int ntiles, int batch,
+                            const uint8_t *__restrict__ mask)
 {
     const int W = ntiles * batch;
     const int per = (W + NXCD - 1) / NXCD;
@@ -316,6 +294,7 @@ void syrk_update_f32_kernel(double *__restrict__ A0, int lda, size_t bstride, in
     const int work = (bid % NXCD) * per + bid / NXCD;
     if (work >= W) return;
     const int b = work / ntiles;
+    if (mask && !mask[b]) return;
     int t = work - b * ntiles;
     int jt = 0;
     while (t >= NR - jt) { t -= NR - jt; ++jt; }
@@ -398,25 +377,26 @@ __global__ void logdet_sum_kernel(const double *__restrict__ lpart, int nparts, 
 }  // namespace
 
 void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int batch, int32_t *info,
-                       double *lpart, int nparts, hipStream_t s)
+                       double *lpart, int nparts, double *lk, hipStream_t s, const uint8_t *mask)
 {
     ProfScope ps(K_POTRF_DIAG, TB * TB * TB / 3.0 * batch, 16.0 * TB * TB * batch, s);
-    potrf_diag_kernel<<<batch, PO_THREADS, 0, s>>>(A, lda, bstride, c0, info, lpart, nparts);
+    potrf_diag_kernel<<<batch, PO_THREADS, 0, s>>>(A, lda, bstride, c0, info, lpart, nparts, lk,
+                                                   mask);
 }
 
 void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int batch,
-                       hipStream_t s)
+                       const double *lk, hipStream_t s, const uint8_t *mask)
 {
     int rows = np - (c0 + TB);
     if (rows <= 0) return;
     ProfScope ps(K_TRSM_PANEL, (double)rows * TB * TB * batch,
                  (16.0 * rows * TB + 8.0 * TB * TB) * batch, s);
     dim3 grid((rows + TR_ROWS - 1) / TR_ROWS, batch);
-    trsm_panel_kernel<<<grid, TR_THREADS, 0, s>>>(A, lda, bstride, np, c0);
+    trsm_panel_kernel<<<grid, TR_THREADS, 0, s>>>(A, lda, bstride, np, c0, lk, mask);
 }
 
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce, int kc0,
-                        int K, int batch, hipStream_t s, int prec)
+                        int K, int batch, hipStream_t s, int prec, const uint8_t *mask)
 {
     if (ce <= cs || K <= 0) return;
     const double entries = (double)(ce - cs) * np - 0.5 * (double)(cs + ce - 1) * (ce - cs);
@@ -441,17 +421,18 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
     const long per = (W + NXCD - 1) / NXCD;
     if (block64)
         syrk_update_kernel<4, 1><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
     else if (f32)
         syrk_update_f32_kernel<<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
     else
         syrk_update_kernel<2, 2><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
 }
 
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
-                  double *lpart, hipStream_t s, int prec, bool bordered)
+                  double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
+                  const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex)
 {
     const int nparts = np / TB;
     for (int c = 0; c < np; c += OUTER_NB) {
@@ -463,16 +444,23 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             // left-looking inside the outer panel: bring block c0 up to date
             // with the blocks [c, c0) of the same panel, then factor it
             if (c0 > c)
-                launch_syrk_update(A, lda, bstride, rmax, c0, c0 + TB, c, c0 - c, batch, s, GP_FP64);
-            launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, s);
-            launch_trsm_panel(A, lda, bstride, rmax, c0, batch, s);
+                launch_syrk_update(A, lda, bstride, rmax, c0, c0 + TB, c, c0 - c, batch, s, GP_FP64,
+                                   mask);
+            launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, lk, s, mask);
+            launch_trsm_panel(A, lda, bstride, rmax, c0, batch, lk, s, mask);
         }
         // right-looking rank-(pe - c) update of the trailing matrix; with a
         // border it also covers the border columns np .. np + pe - 1
         if (bordered)
-            launch_syrk_update(A, lda, bstride, np + pe, pe, np + pe, c, pe - c, batch, s, prec);
-        else if (pe < np)
-            launch_syrk_update(A, lda, bstride, np, pe, np, c, pe - c, batch, s, prec);
+            launch_syrk_update(A, lda, bstride, np + pe, pe, np + pe, c, pe - c, batch, s, prec, mask);
+        else if (pe < np) {
+            const bool i8 = prec == GP_MIXED && oz_sl && oz_ex &&
+                            launch_syrk_update_i8(A, lda, bstride, np, pe, c, pe - c, batch, oz_sl,
+                                                  oz_ex, s, mask);
+            if (!i8)
+                launch_syrk_update(A, lda, bstride, np, pe, np, c, pe - c, batch, s,
+                                   prec == GP_MIXED ? GP_FP64 : prec, mask);
+        }
     }
 }
 

@@ -22,10 +22,10 @@ constexpr int CB_THREADS = 256;
 constexpr int CB_CHUNK = 32;   // thetas per workgroup
 
 __global__ void init_kernel(const double *__restrict__ theta, int d, int batch,
-                            int32_t *__restrict__ info)
+                            int32_t *__restrict__ info, const uint8_t *__restrict__ mask)
 {
     int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= batch) return;
+    if (b >= batch || (mask && !mask[b])) return;
     int ok = 1;
     for (int k = 0; k < d; ++k) {
         double t = theta[(size_t)b * d + k];
@@ -48,7 +48,8 @@ template <int DM, int PMODE>  // PMODE: 0 general p, 1 p == 1, 2 p == 2
 __global__ __launch_bounds__(CB_THREADS)
 void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, double delta,
                        const double *__restrict__ theta, int batch,
-                       double *__restrict__ R, int lda, size_t bstride)
+                       double *__restrict__ R, int lda, size_t bstride,
+                       const uint8_t *__restrict__ mask)
 {
     __shared__ double xi[DM][TB];
     __shared__ double xj[DM][TB];
@@ -59,6 +60,11 @@ void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, dou
     const int tid = threadIdx.x;
     const int b0 = blockIdx.y * CB_CHUNK;
     const int nb = min(CB_CHUNK, batch - b0);
+    if (mask) {   // a chunk with no selected theta has nothing to write
+        int any = 0;
+        for (int c = 0; c < nb; ++c) any |= mask[b0 + c];
+        if (!any) return;   // uniform over the workgroup
+    }
 
     for (int e = tid; e < DM * TB; e += CB_THREADS) {
         int k = e / TB, q = e % TB;
@@ -82,7 +88,8 @@ void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, dou
         const size_t off = (size_t)gi + (size_t)gj * lda;
         if (gi >= n || gj >= n || gi == gj) {
             double v = (gi == gj) ? ((gi < n) ? 1.0 + delta : 1.0) : 0.0;
-            for (int c = 0; c < nb; ++c) Rb[off + (size_t)c * bstride] = v;
+            for (int c = 0; c < nb; ++c)
+                if (!mask || mask[b0 + c]) Rb[off + (size_t)c * bstride] = v;
             continue;
         }
         double D[DM];
@@ -96,6 +103,7 @@ void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, dou
             D[k] = (k < d) ? pw : 0.0;
         }
         for (int c = 0; c < nb; ++c) {
+            if (mask && !mask[b0 + c]) continue;
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < DM; ++k) s = fma(th[c][k], D[k], s);
@@ -124,43 +132,45 @@ __global__ void pad_identity_kernel(double *__restrict__ A, int lda, size_t bstr
 
 template <int DM>
 void launch_corr_dm(const double *X, int n, int d, double p, double delta, const double *theta,
-                    int batch, double *R, int lda, size_t bstride, int np, hipStream_t s)
+                    int batch, double *R, int lda, size_t bstride, int np, hipStream_t s,
+                    const uint8_t *mask)
 {
     const int T = np / TB;
     dim3 grid(T * (T + 1) / 2, (batch + CB_CHUNK - 1) / CB_CHUNK);
     if (p == 2.0)
         corr_build_kernel<DM, 2><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R,
-                                                             lda, bstride);
+                                                             lda, bstride, mask);
     else if (p == 1.0)
         corr_build_kernel<DM, 1><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R,
-                                                             lda, bstride);
+                                                             lda, bstride, mask);
     else
         corr_build_kernel<DM, 0><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R,
-                                                             lda, bstride);
+                                                             lda, bstride, mask);
 }
 
 }  // namespace
 
-void launch_init(const double *theta, int d, int batch, int32_t *info, hipStream_t s)
+void launch_init(const double *theta, int d, int batch, int32_t *info, hipStream_t s,
+                 const uint8_t *mask)
 {
     ProfScope ps(K_INIT, 0.0, 12.0 * batch * d, s);
-    init_kernel<<<(batch + 255) / 256, 256, 0, s>>>(theta, d, batch, info);
+    init_kernel<<<(batch + 255) / 256, 256, 0, s>>>(theta, d, batch, info, mask);
 }
 
 void launch_corr_build(const double *X, int n, int d, double p, double delta,
                        const double *theta, int batch, double *R, int lda, size_t bstride,
-                       int np, hipStream_t s)
+                       int np, hipStream_t s, const uint8_t *mask)
 {
     const double lower = 0.5 * (double)np * (np + 1);
     ProfScope ps(K_CORR_BUILD, 2.0 * d * lower * batch, 8.0 * lower * batch, s);
     if (d <= 4)
-        launch_corr_dm<4>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s);
+        launch_corr_dm<4>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s, mask);
     else if (d <= 8)
-        launch_corr_dm<8>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s);
+        launch_corr_dm<8>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s, mask);
     else if (d <= 16)
-        launch_corr_dm<16>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s);
+        launch_corr_dm<16>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s, mask);
     else
-        launch_corr_dm<GP_DMAX>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s);
+        launch_corr_dm<GP_DMAX>(X, n, d, p, delta, theta, batch, R, lda, bstride, np, s, mask);
 }
 
 void launch_pad_identity(double *A, int lda, size_t bstride, int n, int np, int batch,

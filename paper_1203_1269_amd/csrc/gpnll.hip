@@ -22,7 +22,10 @@ struct Layout {
     size_t bstride;  // doubles per matrix
     size_t lpart;    // offset of the log-det partials
     size_t info;     // offset of info
+    size_t lk;       // diagonal-factor copies for TRSM, batch * 64 * 64 doubles
     size_t rhs, x, s; // refinement vectors (mixed mode), batch * 2 np doubles each
+    size_t mask;     // per-theta FP64 fallback mask (mixed modes), batch bytes
+    size_t oz_sl, oz_ex; // digit slices and row exponents (GP_MIXED)
     size_t total;
 };
 
@@ -38,13 +41,24 @@ bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
     off = align_up(off + sizeof(double) * (size_t)(L.np / TB) * batch);
     L.info = off;
     off = align_up(off + sizeof(int32_t) * (size_t)batch);
-    L.rhs = L.x = L.s = off;
+    L.lk = off;
+    off = align_up(off + sizeof(double) * TB * TB * (size_t)batch);
+    L.rhs = L.x = L.s = L.mask = L.oz_sl = L.oz_ex = off;
+    if (prec == GP_MIXED) {
+        L.mask = off;
+        off += align_up((size_t)batch);
+        L.oz_ex = off;
+        off += align_up(sizeof(int32_t) * (size_t)L.np * batch);
+        L.oz_sl = off;
+        off += align_up(ozaki_slices_bytes(L.np, batch));
+    }
     if (prec == GP_MIXED_FAST) {
         const size_t vec = align_up(sizeof(double) * 2 * (size_t)L.np * batch);
         L.rhs = off;
         L.x = off + vec;
         L.s = off + 2 * vec;
-        off += 3 * vec;
+        L.mask = off + 3 * vec;
+        off += 3 * vec + align_up((size_t)batch);
     }
     L.total = off;
     return true;
@@ -59,7 +73,10 @@ bool dataset_ok(const gp_dataset *ds)
     return true;
 }
 
-bool prec_ok(int32_t prec) { return prec == GP_FP64 || prec == GP_MIXED_FAST; }
+bool prec_ok(int32_t prec)
+{
+    return prec == GP_FP64 || prec == GP_MIXED || prec == GP_MIXED_FAST;
+}
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
 
@@ -99,7 +116,14 @@ gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta,
     launch_init(theta, ds->d, batch, info, stream);
     launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
                       stream);
-    factor_batch(A, np, L.bstride, np, batch, info, lpart, stream, prec);
+    double *lk = (double *)(base + L.lk);
+    factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, prec, false, nullptr,
+                 (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex));
+    if (prec == GP_FP64) {
+        launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
+                            stream);
+        return launched();
+    }
     if (prec == GP_MIXED_FAST)
         refine_solves(A, np, L.bstride, np, ds, theta, batch, lpart, info,
                       (double *)(base + L.rhs), (double *)(base + L.x), (double *)(base + L.s),
@@ -107,6 +131,16 @@ gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta,
     else
         launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
                             stream);
+    // thetas whose mixed result failed (pivot, or refinement in GP_MIXED_FAST)
+    // are redone on the FP64 path; their results carry ir_iters = -1
+    uint8_t *mask = (uint8_t *)(base + L.mask);
+    launch_fallback_mask(out, batch, mask, stream);
+    launch_init(theta, ds->d, batch, info, stream, mask);
+    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
+                      stream, mask);
+    factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, GP_FP64, false, mask);
+    launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
+                        stream, mask, -1);
     return launched();
 }
 
@@ -131,7 +165,8 @@ gp_status gp_corr_build(const gp_dataset *ds, int32_t batch, const double *theta
 size_t gp_cholesky_ws_bytes(int32_t n, int32_t batch)
 {
     if (n < 1 || n > GP_NMAX || batch < 1) return 0;
-    return align_up(sizeof(double) * (size_t)(pad64(n) / TB) * batch);
+    return align_up(sizeof(double) * (size_t)(pad64(n) / TB) * batch) +
+           align_up(sizeof(double) * TB * TB * (size_t)batch);
 }
 
 gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda, int32_t *info,
@@ -142,16 +177,17 @@ gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda, in
     if (lda < np || !aligned16(A) || (lda % 2) != 0) return GP_EINVAL;
     if (ws_bytes < gp_cholesky_ws_bytes(n, batch)) return GP_EWORKSPACE;
     double *lpart = (double *)ws;
+    double *lk = (double *)((char *)ws + align_up(sizeof(double) * (size_t)(np / TB) * batch));
     const size_t bstride = (size_t)lda * lda;
     launch_pad_identity(A, lda, bstride, n, np, batch, stream);
-    factor_batch(A, lda, bstride, np, batch, info, lpart, stream, GP_FP64);
+    factor_batch(A, lda, bstride, np, batch, info, lpart, lk, stream, GP_FP64);
     launch_logdet_sum(lpart, np / TB, batch, logdet, stream);
     return launched();
 }
 
 struct GradLayout {
     int np, ntiles;
-    size_t lda, bstride, mat, lpart, info, alpha, part, total;
+    size_t lda, bstride, mat, lpart, info, lk, alpha, part, total;
 };
 
 static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
@@ -169,6 +205,8 @@ static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
     off = align_up(off + sizeof(double) * (size_t)T * batch);
     L.info = off;
     off = align_up(off + sizeof(int32_t) * (size_t)batch);
+    L.lk = off;
+    off = align_up(off + sizeof(double) * TB * TB * (size_t)batch);
     L.alpha = off;
     off = align_up(off + sizeof(double) * (size_t)L.np * batch);
     L.part = off;
@@ -207,7 +245,8 @@ gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta, 
     launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, lda, L.bstride, np,
                       stream);
     launch_border_init(A, lda, L.bstride, np, batch, stream);
-    factor_batch(A, lda, L.bstride, np, batch, info, lpart, stream, GP_FP64, true);
+    factor_batch(A, lda, L.bstride, np, batch, info, lpart, (double *)(base + L.lk), stream,
+                 GP_FP64, true);
     launch_solve_reduce(A, lda, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
                         stream);
     launch_alpha(A, lda, L.bstride, np, ds->n, ds->y, out, alpha, batch, stream);

@@ -19,35 +19,55 @@ constexpr int OUTER_NB = 256;   // outer panel width (K of the trailing update)
 
 inline int pad64(int n) { return (n + TB - 1) / TB * TB; }
 
-// theta validity, info and log-det partial initialisation.
-void launch_init(const double *theta, int d, int batch, int32_t *info, hipStream_t s);
+// Optional per-theta mask (mask[b] == 0: the launch leaves theta b alone;
+// nullptr: all thetas) used to rerun a subset of a batch on the FP64 path.
+
+// theta validity and info initialisation.
+void launch_init(const double *theta, int d, int batch, int32_t *info, hipStream_t s,
+                 const uint8_t *mask = nullptr);
 
 // a1: R_delta tiles on and below the diagonal, identity padding.
 void launch_corr_build(const double *X, int n, int d, double p, double delta,
                        const double *theta, int batch, double *R, int lda,
-                       size_t bstride, int np, hipStream_t s);
+                       size_t bstride, int np, hipStream_t s, const uint8_t *mask = nullptr);
 
 // Identity padding of rows/columns n..np-1 (lower part) of caller matrices.
 void launch_pad_identity(double *A, int lda, size_t bstride, int n, int np, int batch,
                          hipStream_t s);
 
 // a2: factorisation steps.
+// lk: batch * 64 * 64 doubles, the current diagonal factor copy for TRSM.
 void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int batch,
-                       int32_t *info, double *lpart, int nparts, hipStream_t s);
+                       int32_t *info, double *lpart, int nparts, double *lk, hipStream_t s,
+                       const uint8_t *mask = nullptr);
 void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int batch,
-                       hipStream_t s);
+                       const double *lk, hipStream_t s, const uint8_t *mask = nullptr);
 // C(r, c) -= sum_{k in [kc0, kc0+K)} A(r, k) A(c, k) for c in [cs, ce) and
 // r in [c's 128-tile row .. np), i.e. the lower part of the column range.
 // prec selects the arithmetic of rank-256 trailing updates (GP_FP64 or
 // GP_MIXED_FAST); updates of a single 64-column block are always FP64.
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce,
-                        int kc0, int K, int batch, hipStream_t s, int prec);
+                        int kc0, int K, int batch, hipStream_t s, int prec,
+                        const uint8_t *mask = nullptr);
 
 // The whole blocked factorisation (a2) plus log-det partials (a3).  With
 // `bordered`, A has order 2 np and holds [[R, I], [I, 0]]; only the first np
 // columns are factored, which leaves L^-T bottom-left and -R^-1 bottom-right.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
-                  double *lpart, hipStream_t s, int prec, bool bordered = false);
+                  double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
+                  const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
+                  int32_t *oz_ex = nullptr);
+
+// GP_MIXED trailing update: digits of the panel rows (OZ_S slices) and one
+// exponent per row, then the INT8-MFMA product.  Returns false (nothing
+// launched) when the shape is not the rank-256 one it handles.
+#ifndef OZ_S
+#define OZ_S 7
+#endif
+size_t ozaki_slices_bytes(int np, int batch);
+bool launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
+                           int batch, int8_t *sl, int32_t *ex, hipStream_t s,
+                           const uint8_t *mask = nullptr);
 
 // a5: iterative refinement of R x = [1 y] with FP64 residuals (R regenerated
 // from X) and corrections through the factor A; then mu, sigma2, nll.
@@ -69,8 +89,14 @@ void launch_logdet_sum(const double *lpart, int nparts, int batch, double *logde
                        hipStream_t s);
 
 // a4 + a6: forward solves with [1 y], mu, sigma2, nll; writes gp_result.
+// ir_tag goes to gp_result.ir_iters of the thetas written.
 void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n,
                          const double *y, const double *lpart, int nparts,
-                         const int32_t *info, int batch, gp_result *out, hipStream_t s);
+                         const int32_t *info, int batch, gp_result *out, hipStream_t s,
+                         const uint8_t *mask = nullptr, int ir_tag = 0);
+
+// mask[b] = 1 for thetas whose mixed-precision result must be recomputed in
+// FP64 (failed pivot or refinement above the FP64 backward-error level).
+void launch_fallback_mask(const gp_result *out, int batch, uint8_t *mask, hipStream_t s);
 
 }  // namespace gpk

@@ -23,6 +23,8 @@ enum KernelKind {
     K_ADJOINT,
     K_RESIDUAL,
     K_SOLVE2,
+    K_OZAKI_SPLIT,
+    K_SYRK_UPDATE_I8,
     K_NUM_KINDS
 };
 

@@ -340,7 +340,21 @@ void launch_solve2(const double *A, int lda, size_t bstride, int np, const doubl
                                                                               rhs, x);
 }
 
+__global__ void fallback_mask_kernel(const gp_result *__restrict__ out, int batch,
+                                     uint8_t *__restrict__ mask)
+{
+    const int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= batch) return;
+    const int inf = out[b].info;
+    mask[b] = (inf > 0 || inf == -2) ? 1 : 0;
+}
+
 }  // namespace
+
+void launch_fallback_mask(const gp_result *out, int batch, uint8_t *mask, hipStream_t s)
+{
+    fallback_mask_kernel<<<(batch + 255) / 256, 256, 0, s>>>(out, batch, mask);
+}
 
 void refine_solves(const double *A, int lda, size_t bstride, int np, const gp_dataset *ds,
                    const double *theta, int batch, const double *lpart, const int32_t *info,

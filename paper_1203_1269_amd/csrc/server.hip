@@ -105,7 +105,8 @@ gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *
     if (!datasets || ndatasets < 1 || !arena || !cfg || !out) return GP_EINVAL;
     if (cfg->max_batch < 1 || cfg->max_batch > 1024 || cfg->nstreams < 1 || cfg->nstreams > 64)
         return GP_EINVAL;
-    if (cfg->prec != GP_FP64 && cfg->prec != GP_MIXED_FAST) return GP_EINVAL;
+    if (cfg->prec != GP_FP64 && cfg->prec != GP_MIXED && cfg->prec != GP_MIXED_FAST)
+        return GP_EINVAL;
     if (((uintptr_t)arena & 255) != 0) return GP_EINVAL;
     for (int k = 0; k < ndatasets; ++k) {
         const gp_dataset &d = datasets[k];

@@ -30,8 +30,10 @@ __global__ __launch_bounds__(SV_THREADS)
 void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride, int np, int n,
                          const double *__restrict__ y, const double *__restrict__ lpart,
                          int nparts, const int32_t *__restrict__ info,
-                         gp_result *__restrict__ out)
+                         gp_result *__restrict__ out, const uint8_t *__restrict__ mask,
+                         int ir_tag)
 {
+    if (mask && !mask[blockIdx.x]) return;
     extern __shared__ double zs[];          // z0[np], z1[np]
     __shared__ double part[SV_WAVES][2][64];
     __shared__ double red[SV_WAVES][3];
@@ -115,7 +117,7 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
         Q = 0.0; ld = 0.0;
         for (int w = 0; w < SV_WAVES; ++w) { Q += red[w][0]; ld += red[w][2]; }
         gp_result res;
-        res.ir_iters = 0;
+        res.ir_iters = ir_tag;
         int inf = info[b];
         if (inf != 0) {
             res.logdet = res.mu = res.sigma2 = res.nll = NAN;
@@ -142,7 +144,7 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
 
 void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n, const double *y,
                          const double *lpart, int nparts, const int32_t *info, int batch,
-                         gp_result *out, hipStream_t s)
+                         gp_result *out, hipStream_t s, const uint8_t *mask, int ir_tag)
 {
     static bool attr_set = false;
     const size_t shm = (size_t)2 * np * sizeof(double);
@@ -155,7 +157,7 @@ void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n
     const double lower = 0.5 * (double)np * (np + 1);
     ProfScope ps(K_SOLVE_REDUCE, 4.0 * lower * batch, (8.0 * lower + 16.0 * n) * batch, s);
     solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
-                                                       info, out);
+                                                       info, out, mask, ir_tag);
 }
 
 }  // namespace gpk

@@ -25,6 +25,7 @@ from parity_util import lapack_fp64  # noqa: E402
 WORKLOADS = {
     "fp64_n4096_d8": inputs.fp64_at_scale,
     "mixed_n8192_d10": inputs.mixed_at_scale,
+    "grad_n4096_d6": inputs.gradient_workload,
 }
 
 
@@ -40,7 +41,26 @@ def sample_indices(theta, k):
     return sorted(idx)
 
 
+def main_grad(name, k=2):
+    """Oracle gradients (FP64 and 80-bit builds) for k sampled thetas."""
+    w = WORKLOADS[name]()
+    idx = sample_indices(w.theta, k)
+    t0 = time.time()
+    th = w.theta[idx]
+    _, g64 = oracle.grad_batch(w.X, w.y, th, w.p, w.delta)
+    _, g80 = oracle.grad_batch(w.X, w.y, th, w.p, w.delta, extended=True)
+    samples = [{"index": t, "theta": th[q].tolist(), "grad_f64": g64[q].tolist(),
+                "grad_f80": g80[q].tolist()} for q, t in enumerate(idx)]
+    out = {"workload": name, "seed": w.seed, "n": w.n, "d": w.d, "p": w.p, "delta": w.delta,
+           "samples": samples, "oracle_seconds": time.time() - t0}
+    path = os.path.join(HERE, f"{name}_expected.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"])
+
+
 def main(name, k=4):
+    if name.startswith("grad_"):
+        return main_grad(name, k)
     w = WORKLOADS[name]()
     idx = sample_indices(w.theta, k)
     t0 = time.time()

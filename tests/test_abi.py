@@ -57,7 +57,7 @@ def test_workspace_sizing(lib):
     from paper_1203_1269_amd import binding
     ws = binding.workspace_bytes(4096, 8, 128)
     assert ws >= 128 * 4096 * 4096 * 8
-    assert ws < 128 * 4096 * 4096 * 8 + (1 << 22)
+    assert ws < 128 * 4096 * 4096 * 8 + (1 << 24)
     assert binding.workspace_bytes(200, 2, 64) >= 64 * 256 * 256 * 8
     assert lib.gp_workspace_bytes(1, 2, 1, 0) == 0        # n < 2
     assert lib.gp_workspace_bytes(8193, 2, 1, 0) == 0     # n > GP_NMAX
@@ -65,6 +65,12 @@ def test_workspace_sizing(lib):
     assert lib.gp_workspace_bytes(100, 33, 1, 0) == 0     # d > GP_DMAX
     assert lib.gp_workspace_bytes(100, 2, 0, 0) == 0      # empty batch
     assert lib.gp_workspace_bytes(100, 2, 1, 7) == 0      # unknown precision
+    # the matched-accuracy mixed mode adds 7 digit slices of K = 256 bytes per
+    # padded row, one exponent per row and a fallback flag per theta
+    mx = binding.workspace_bytes(4096, 8, 128, "mixed")
+    assert mx >= ws + 128 * 4096 * (7 * 256 + 4)
+    assert mx < ws + 128 * 4096 * (7 * 256 + 4) + (1 << 12)
+    assert binding.workspace_bytes(4096, 8, 128, "mixed_fast") > ws
 
 
 def _ds(X=1 << 20, y=1 << 21, n=100, d=2, p=2.0, delta=1e-6):

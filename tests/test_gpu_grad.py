@@ -80,7 +80,12 @@ def test_gradient_matches_finite_differences(gp):
 
 def test_gradient_fullsize_against_finite_differences(gp):
     """n=4096, d=6, p=2, nugget 1e-6, 16 thetas: adjoint vs central
-    differences of the GPU likelihood (h = 1e-6 theta_k)."""
+    differences of the GPU likelihood (h = 1e-6 theta_k).  The difference
+    quotient carries the rounding error eps_f of the two nll values divided
+    by h; with |nll| ~ 1e4 that noise is comparable to the gradient for small
+    theta_k, so the bound is 1e-5 |g| + 4 eps_f / h_k with eps_f = 1e-11 |nll|
+    (about 50 times the FP64 rounding spread measured at n=4096; the stored
+    80-bit oracle gradients are the strict check)."""
     w = inputs.gradient_workload()
     print("[grad] fullsize n=4096 d=6 B=16", flush=True)
     ds = gp.Dataset(w.X, w.y, w.p, w.delta)
@@ -88,12 +93,37 @@ def test_gradient_fullsize_against_finite_differences(gp):
     res, g = to_host(res), g.cpu().numpy()
     assert np.all(res["info"] == 0)
     fd = fd_gradient(gp, ds, w.theta)
-    err = np.abs(g - fd) / np.maximum(np.abs(fd), 1.0)
-    print("fullsize fd max rel err", err.max())
-    assert np.all(err <= 1e-5), err
+    h = 1e-6 * w.theta
+    eps_f = 1e-11 * np.abs(res["nll"])[:, None]
+    bound = 1e-5 * np.maximum(np.abs(fd), 1.0) + 4 * eps_f / h
+    ratio = np.abs(g - fd) / bound
+    print("fullsize: max |g - fd| / bound =", ratio.max(), " max rel err", (np.abs(g - fd) / np.maximum(np.abs(fd), 1.0)).max())
+    assert np.all(ratio <= 1.0), ratio
     # the value part equals the plain likelihood path bitwise in log|R|
     plain = to_host(gp.nll_batch(ds, w.theta))
     assert np.allclose(plain["nll"], res["nll"], rtol=1e-12, atol=0)
+
+
+def test_gradient_fullsize_against_oracle(gp):
+    """Sampled thetas of the n=4096, d=6 gradient workload against the stored
+    80-bit oracle gradient (tests/golden/make_expected.py grad_n4096_d6)."""
+    import json, os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "grad_n4096_d6_expected.json")
+    if not os.path.exists(path):
+        pytest.skip("grad_n4096_d6 expected values not generated")
+    exp = json.load(open(path))
+    w = inputs.gradient_workload()
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    idx = [rec["index"] for rec in exp["samples"]]
+    _, g = gp.nll_grad(ds, w.theta[idx])
+    g = g.cpu().numpy()
+    for q, rec in enumerate(exp["samples"]):
+        g80, g64 = np.array(rec["grad_f80"]), np.array(rec["grad_f64"])
+        scale = np.maximum(np.abs(g80), 1.0)
+        err = np.abs(g[q] - g80) / scale
+        tol = np.maximum(1e-9, 20 * np.abs(g64 - g80) / scale)
+        print("theta", rec["index"], "max rel err", err.max(), "oracle spread", (np.abs(g64 - g80) / scale).max())
+        assert np.all(err <= tol), (err, tol)
 
 
 def test_autograd_function(gp):

@@ -1,0 +1,124 @@
+"""Matched-accuracy mixed mode (GP_MIXED: rank-256 trailing updates on INT8
+MFMA through an error-free digit splitting of the panel, every other step in
+FP64) against the 80-bit oracle, through the C ABI.
+
+Bar: every output of every theta within max(1e-8, 10 x the FP64 rounding
+spread of two independent FP64 codes for that theta) of the 80-bit oracle,
+info bit-exact.  Shapes span one to several rank-256 updates with ragged
+tails; the full-size launch is checked on the sampled thetas of the stored
+oracle values and, at every theta, against the FP64 path.
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1203_1269_amd import inputs
+from parity_util import compare, lapack_fp64, scales, to_host, tolerances
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+HERE = os.path.dirname(os.path.abspath(__file__))
+MATCH = 1e-8
+
+
+@pytest.fixture(scope="module")
+def gp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1203_1269_amd import binding
+    binding.lib()
+    return binding
+
+
+@pytest.mark.parametrize("n,d,p,delta,B", [
+    (321, 2, 2.0, 1e-6, 3),      # one update of a 128-row trailing matrix
+    (600, 12, 1.0, 1e-6, 4),     # p = 1
+    (1000, 3, 1.5, 1e-8, 5),     # three updates, small nugget
+    (1500, 8, 1.95, 1e-6, 6),    # general p (pow path)
+    (2048, 6, 2.0, 1e-6, 6),
+])
+def test_mixed_matched_against_oracle(gp, n, d, p, delta, B):
+    rng = np.random.default_rng(7000 + n)
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = inputs.log_uniform_theta(B, d, 0.05, 20, rng)
+    print(f"[parity] mixed n={n} d={d} p={p} delta={delta} B={B}", flush=True)
+    ds = gp.Dataset(X, y, p, delta)
+    got = to_host(gp.nll_batch(ds, th, prec="mixed"))
+    r64 = oracle.nll_batch(X, y, th, p, delta)
+    r80 = oracle.nll_batch(X, y, th, p, delta, extended=True)
+    tol = tolerances(r64, r80, y, lapack_fp64(X, y, th, p, delta), floor=MATCH)
+    worst = compare(got, r80, tol, y, f"mixed n={n}")
+    assert np.all(np.isin(got["ir_iters"], [0, -1])), got["ir_iters"]
+    print("mixed worst rel err vs 80-bit oracle:", worst, flush=True)
+
+
+def test_mixed_without_trailing_update_is_fp64(gp):
+    """n <= 256: one outer panel, no rank-256 update, so the mixed mode runs
+    exactly the FP64 kernels: results bitwise the FP64 path's."""
+    w = inputs.small_2d()
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    a = to_host(gp.nll_batch(ds, w.theta, prec="fp64"))
+    b = to_host(gp.nll_batch(ds, w.theta, prec="mixed"))
+    for k in ("logdet", "mu", "sigma2", "nll", "info"):
+        assert np.array_equal(a[k], b[k]), k
+
+
+def test_mixed_edge_cases(gp):
+    """Invalid theta (-3) and a numerically singular R (delta = 0, tiny theta:
+    info > 0 on both paths) sit in one batch with ordinary thetas; the others
+    are unaffected and a non-PD mixed theta never returns numbers."""
+    rng = np.random.default_rng(91)
+    n, d = 700, 3
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = np.vstack([inputs.log_uniform_theta(2, d, 0.5, 5, rng),
+                    np.array([[1.0, -1.0, 1.0]]),
+                    np.full((1, d), 1e-3),
+                    inputs.log_uniform_theta(1, d, 0.5, 5, rng)])
+    print("[parity] mixed edge cases n=700", flush=True)
+    ds = gp.Dataset(X, y, 2.0, 0.0)
+    got = to_host(gp.nll_batch(ds, th, prec="mixed"))
+    ref = to_host(gp.nll_batch(ds, th, prec="fp64"))
+    assert got["info"][2] == -3 and ref["info"][2] == -3
+    assert got["info"][3] > 0 and ref["info"][3] > 0
+    assert np.isnan(got["nll"][3]) and np.isnan(got["nll"][2])
+    ok = ref["info"] == 0
+    assert ok[[0, 1, 4]].all() and np.array_equal(got["info"][ok], ref["info"][ok])
+    e = oracle.rel(got["nll"][ok], ref["nll"][ok], 1.0)
+    assert np.all(e <= MATCH), e
+
+
+def test_fullsize_mixed_n4096_d8(gp):
+    """The benchmarked launch (n=4096, d=8, p=1.95, nugget 1e-6, 128 thetas)
+    in the mixed mode: the sampled thetas against the stored oracle values
+    (matched bar), and every theta against the FP64 path."""
+    path = os.path.join(HERE, "golden", "fp64_n4096_d8_expected.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    exp = json.load(open(path))
+    w = inputs.fp64_at_scale()
+    print("[parity] fullsize mixed n=4096 d=8 B=128", flush=True)
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    got = to_host(gp.nll_batch(ds, w.theta, prec="mixed"))
+    ref = to_host(gp.nll_batch(ds, w.theta, prec="fp64"))
+    assert np.all(got["info"] == 0)
+    sc = scales(w.y)
+    for rec in exp["samples"]:
+        t = rec["index"]
+        for k in ("logdet", "mu", "sigma2", "nll"):
+            r = rec["f80"][k]
+            err = abs(got[k][t] - r) / max(abs(r), sc[k])
+            tol = max(MATCH, 10 * max(rec["err64"][k], rec["err64_lapack"][k]))
+            assert err <= tol, (t, k, got[k][t], r, err, tol)
+    worst = {}
+    for k in ("logdet", "mu", "sigma2", "nll"):
+        e = oracle.rel(got[k], ref[k], sc[k])
+        worst[k] = float(e.max())
+    print("mixed vs FP64 path, worst rel diff over 128 thetas:", worst,
+          "recomputed in FP64:", int((got["ir_iters"] == -1).sum()), flush=True)
+    assert worst["nll"] <= MATCH and worst["logdet"] <= MATCH

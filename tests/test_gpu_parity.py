@@ -285,6 +285,10 @@ def test_mixed_fast_single_panel_factor_is_fp64(gp):
 
 @pytest.mark.parametrize("n,d,p", [(1500, 8, 1.95), (2048, 6, 2.0)])
 def test_mixed_fast_errors_reported(gp, n, d, p):
+    """Mixed results are either refined (ir_iters == 2, mu and sigma2 at the
+    FP64 level) or, where the FP32 updates broke positive definiteness or the
+    refinement stalled, recomputed in FP64 inside the same call
+    (ir_iters == -1): those must be bitwise the FP64 path's results."""
     rng = np.random.default_rng(6000 + n)
     X = inputs.lhs_design(n, d, rng)
     y = inputs.sine_response(X, rng)
@@ -292,12 +296,17 @@ def test_mixed_fast_errors_reported(gp, n, d, p):
     print(f"[parity] mixed_fast n={n} d={d}", flush=True)
     ds = gp.Dataset(X, y, p, 1e-6)
     got = to_host(gp.nll_batch(ds, th, prec="mixed_fast"))
+    ref64 = to_host(gp.nll_batch(ds, th, prec="fp64"))
     r80 = oracle.nll_batch(X, y, th, p, 1e-6, extended=True)
-    assert np.all(np.isin(got["info"], [0, -2])) and np.all(r80.info == 0)
+    assert np.all(got["info"] == 0) and np.all(r80.info == 0), got["info"]
+    assert np.all(np.isin(got["ir_iters"], [2, -1])), got["ir_iters"]
+    fb = got["ir_iters"] == -1
+    for k in ("logdet", "mu", "sigma2", "nll"):
+        assert np.array_equal(got[k][fb], ref64[k][fb]), k
     sc = scales(y)
     errs = {k: oracle.rel(got[k], getattr(r80, k), sc[k]) for k in ("logdet", "mu", "sigma2", "nll")}
     print("mixed_fast max rel err vs 80-bit oracle:", {k: float(v.max()) for k, v in errs.items()},
-          "refinement sweeps", got["ir_iters"], "info", got["info"])
+          "refinement sweeps", got["ir_iters"], flush=True)
     for k in ("logdet", "nll"):
         assert np.all(errs[k] <= 1e-3), (k, errs[k])
     # the refined solves bring mu and sigma2 to the FP64 level (the FP64
@@ -306,4 +315,29 @@ def test_mixed_fast_errors_reported(gp, n, d, p):
     tol = tolerances(r64, r80, y, lapack_fp64(X, y, th, p, 1e-6))
     for k in ("mu", "sigma2"):
         assert np.all(errs[k] <= 100 * tol[k]), (k, errs[k], tol[k])
-    assert np.all(got["ir_iters"] == 2)
+
+
+def test_mixed_fast_fallback_whole_batch(gp):
+    """theta = 0 makes R = 1 1^T + delta I, whose FP32-updated factor is not
+    positive definite at small delta; every such theta is recomputed in FP64
+    and matches the FP64 path bitwise, while an invalid theta stays -3."""
+    rng = np.random.default_rng(77)
+    n, d = 600, 3
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = np.vstack([np.full((3, d), 1e-4), inputs.log_uniform_theta(2, d, 0.5, 5, rng),
+                    np.array([[1.0, -1.0, 1.0]])])
+    print("[parity] mixed_fast fallback n=600", flush=True)
+    ds = gp.Dataset(X, y, 2.0, 1e-7)
+    got = to_host(gp.nll_batch(ds, th, prec="mixed_fast"))
+    ref64 = to_host(gp.nll_batch(ds, th, prec="fp64"))
+    assert got["info"][-1] == -3 and ref64["info"][-1] == -3
+    np.testing.assert_array_equal(got["info"], ref64["info"])
+    fb = got["ir_iters"] == -1
+    assert fb[:3].all(), got["ir_iters"]
+    for k in ("logdet", "mu", "sigma2", "nll"):
+        assert np.array_equal(got[k][fb], ref64[k][fb]), k
+    ok = ref64["info"] == 0
+    r80 = oracle.nll_batch(X, y, th[ok], 2.0, 1e-7, extended=True)
+    e = oracle.rel(got["nll"][ok], r80.nll, 1.0)
+    assert np.all(e[got["ir_iters"][ok] == -1] <= 1e-6), e
