@@ -33,17 +33,22 @@ SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
 # workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # what the same counters read for a 512 MiB device copy (bench.py
 # --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).
-# Valid only for the kernel text it was taken on: reported as null once the
-# sha256 of that kernel's source differs.
+# Valid only for the kernel and launch loop it was taken on: reported as null
+# once the sha256 of their source differs.
 SYRK_TRAFFIC = {"kernel_sha256": "5d1ce42c1d506d4f0d69b2aa52d1066c54f5538fb69f4b8dd62f218c2a93cfa8",
                 "bytes_per_launch": (2.0 * 4.36e7 + 1.0 * 4.162e7) / 15 * 1024}
 
 
 def syrk_kernel_text():
+    """Source of the trailing-update kernel and of the host loop that
+    launches it (the launch shapes decide the per-launch traffic)."""
     with open(SYRK_SRC) as f:
         src = f.read()
-    i = src.index("void syrk_update_kernel(")
-    return src[i:src.index("\n}\n", i) + 3]
+    parts = []
+    for start in ("void syrk_update_kernel(", "void factor_batch("):
+        i = src.index(start)
+        parts.append(src[i:src.index("\n}\n", i) + 3])
+    return "".join(parts)
 
 
 def parse():
@@ -167,8 +172,13 @@ def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps):
     if prec == "mixed":
         sy = kst.get("syrk_update_i8", {"flops": 0.0, "ms": 1.0})
         out["trailing_update_fp64_equiv_tflops"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12
-        # INT8 MFMA operations actually issued: 28 digit pairs per FP64 product
-        out["trailing_update_int8_tops"] = 28 * sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+        # INT8 MFMA operations actually issued: S(S+1)/2 digit pairs per FP64 product
+        from paper_1203_1269_amd import binding
+        S = binding.header_constant("GP_MIXED_DIGITS")
+        pairs = S * (S + 1) // 2
+        out["digits"] = S
+        out["trailing_update_int8_tops"] = pairs * sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+        out["trailing_update_frac_of_int8_peak"] = out["trailing_update_int8_tops"] / 5000.0
     else:
         sy = kst.get("syrk_update_f32", {"flops": 0.0, "ms": 1.0})
         out["trailing_update_tflops_fp32_mfma"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12

@@ -47,6 +47,7 @@ extern "C" {
 
 #define GP_NMAX 8192
 #define GP_DMAX 32
+#define GP_MIXED_DIGITS 8   /* digits per panel entry in GP_MIXED */
 
 typedef enum {
     GP_OK = 0,
@@ -59,13 +60,15 @@ typedef enum {
     GP_FP64 = 0,         /* every step in FP64 (FP64 MFMA for the trailing updates) */
     GP_MIXED = 1,        /* matched accuracy: the rank-256 trailing updates
                             C -= P P^T run on INT8 MFMA through an error-free
-                            splitting of P (per-row power-of-two scale, 7
-                            signed 7-bit digits, the 28 digit pairs of
-                            combined weight >= 2^-63 accumulated exactly in
-                            INT32 and combined in FP64); every other step in
-                            FP64.  About 49 significant bits per update
-                            relative to the row scales: -2logL agrees with
-                            the FP64 path well within 1e-8 relative.  A theta
+                            splitting of P (per-row power-of-two scale,
+                            GP_MIXED_DIGITS signed 7-bit digits, the digit
+                            pairs of combined weight >= 2^-(7 GP_MIXED_DIGITS
+                            + 7) accumulated exactly in INT32 and combined in
+                            FP64); every other step in FP64.  The update
+                            carries about 7 GP_MIXED_DIGITS significant bits
+                            relative to the row scales (56, as many as the
+                            FP64 update): -2logL and log|R| agree with the
+                            FP64 path well within 1e-8 relative.  A theta
                             whose factorisation loses positive definiteness
                             is recomputed on the FP64 path within the same
                             call (gp_result.ir_iters = -1). */

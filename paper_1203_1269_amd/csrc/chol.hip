@@ -14,6 +14,10 @@
 // keeps it above the FP64 ridge of the chip (78.6 TFLOP/s over 8 TB/s).
 #include <math.h>
 
+#include <map>
+#include <mutex>
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace gpk {
@@ -181,6 +185,9 @@ void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
 
 constexpr int SY_THREADS = 256;
 constexpr int NXCD = 8;
+#ifndef SY_NSETS
+#define SY_NSETS 4   // fragment sets in flight (prefetch distance in k-steps of 4)
+#endif
 
 // WR x WC waves of 64 x 64: <2,2> = 128 x 128 tiles over a lower-triangular
 // column range; <4,1> = 256 x 64 tiles over a single 64-wide column block.
@@ -214,15 +221,18 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
     const int li = lane & 15, lk = lane >> 4;
     const int pli = 4 * (li & 3) + (li >> 2);   // permuted A row of this lane
 
-    // operand pointers and the first two k-steps of fragments go out first
+    // operand pointers; the fragments of the first SY_NSETS k-steps go out first
     const double *pa = A + (size_t)(r0 + pli) + (size_t)(kc0 + lk) * lda;
     const double *pb = A + (size_t)(c0 + li) + (size_t)(kc0 + lk) * lda;
     const size_t step4 = (size_t)4 * lda;
-    double a0[4], b0[4], a1[4], b1[4];
+    double fa[SY_NSETS][4], fb[SY_NSETS][4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+    for (int st = 0; st < SY_NSETS; ++st)
 #pragma unroll
-    for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
+        for (int q = 0; q < 4; ++q) {
+            fa[st][q] = pa[st * step4 + 16 * q];
+            fb[st][q] = pb[st * step4 + 16 * q];
+        }
 
     // accumulators start at -C and gather +A(r,k) A(c,k): no per-step negation
     dbl4 acc[4][4];
@@ -236,31 +246,28 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
             acc[rb][cb] = -(dbl4){lo.x, lo.y, hi.x, hi.y};
         }
 
-    // K is a multiple of 64: two k-steps per trip, each fragment set reloaded
-    // for the trip after next right after its MFMAs were issued
-    for (int kk = 0; kk < K; kk += 8) {
+    // K is a multiple of 4 SY_NSETS: SY_NSETS k-steps per trip, each
+    // fragment set reloaded for the trip after this one right after its
+    // MFMAs were issued (prefetch distance SY_NSETS k-steps)
+    for (int kk = 0; kk < K; kk += 4 * SY_NSETS) {
 #pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
+        for (int st = 0; st < SY_NSETS; ++st) {
 #pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0[rb], b0[cb], acc[rb][cb],
-                                                                   0, 0, 0);
-        pa += 2 * step4;
-        pb += 2 * step4;
-        if (kk + 8 < K) {
+            for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+                for (int cb = 0; cb < 4; ++cb)
+                    acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[st][rb], fb[st][cb],
+                                                                       acc[rb][cb], 0, 0, 0);
+            if (kk + 4 * (SY_NSETS + st) < K) {
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    fa[st][q] = pa[(SY_NSETS + st) * step4 + 16 * q];
+                    fb[st][q] = pb[(SY_NSETS + st) * step4 + 16 * q];
+                }
+            }
         }
-#pragma unroll
-        for (int rb = 0; rb < 4; ++rb)
-#pragma unroll
-            for (int cb = 0; cb < 4; ++cb)
-                acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1[rb], b1[cb], acc[rb][cb],
-                                                                   0, 0, 0);
-        if (kk + 12 < K) {
-#pragma unroll
-            for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
-        }
+        pa += SY_NSETS * step4;
+        pb += SY_NSETS * step4;
     }
 
 #pragma unroll
@@ -430,11 +437,55 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
             A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
 }
 
+namespace {
+
+// Side stream (and fork/join events) for the lookahead of one caller stream,
+// created on first use per (device, caller stream) and kept for the life of
+// the process.  Default priority, non-blocking.
+struct SideStream {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
+};
+
+SideStream *side_for(hipStream_t caller)
+{
+    static std::mutex mu;
+    static std::map<std::pair<int, hipStream_t>, SideStream> table;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lock(mu);
+    auto key = std::make_pair(dev, caller);
+    auto it = table.find(key);
+    if (it != table.end()) return it->second.s ? &it->second : nullptr;
+    SideStream sd;
+    if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) {
+        // no lookahead for this stream; remember the failure
+        table[key] = SideStream{};
+        return nullptr;
+    }
+    table[key] = sd;
+    return &table[key];
+}
+
+}  // namespace
+
+// Blocked right-looking Cholesky with a one-panel lookahead: after outer
+// panel [c, pe) is factored, the trailing update is split at the end of the
+// next panel.  The next panel's columns are updated on the caller's stream
+// and factored there while the rest of the trailing matrix is updated on a
+// side stream; the caller's stream waits for that update before it touches
+// the same columns (the next trailing update).  The two streams write
+// disjoint column ranges and read only finished panels, so the result is the
+// same operations in the same order per entry as without the lookahead.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
                   const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex)
 {
     const int nparts = np / TB;
+    SideStream *sd = (bordered || np > 2 * OUTER_NB) ? side_for(s) : nullptr;
+    bool pending = false;   // the side stream holds an update not yet joined
     for (int c = 0; c < np; c += OUTER_NB) {
         const int pe = min(c + OUTER_NB, np);
         for (int c0 = c; c0 < pe; c0 += TB) {
@@ -449,19 +500,41 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, lk, s, mask);
             launch_trsm_panel(A, lda, bstride, rmax, c0, batch, lk, s, mask);
         }
-        // right-looking rank-(pe - c) update of the trailing matrix; with a
-        // border it also covers the border columns np .. np + pe - 1
-        if (bordered)
-            launch_syrk_update(A, lda, bstride, np + pe, pe, np + pe, c, pe - c, batch, s, prec, mask);
-        else if (pe < np) {
-            const bool i8 = prec == GP_MIXED && oz_sl && oz_ex &&
-                            launch_syrk_update_i8(A, lda, bstride, np, pe, c, pe - c, batch, oz_sl,
-                                                  oz_ex, s, mask);
-            if (!i8)
-                launch_syrk_update(A, lda, bstride, np, pe, np, c, pe - c, batch, s,
-                                   prec == GP_MIXED ? GP_FP64 : prec, mask);
+        // right-looking rank-(pe - c) update of the trailing matrix: rows up
+        // to rlim, columns [pe, cend); with a border it also covers the
+        // border columns np .. np + pe - 1
+        const int rlim = bordered ? np + pe : np;
+        const int cend = bordered ? np + pe : np;
+        if (cend <= pe) continue;
+        if (pending) {
+            (void)hipStreamWaitEvent(s, sd->join, 0);
+            pending = false;
         }
+        const int K = pe - c;
+        const bool i8 = prec == GP_MIXED && !bordered && oz_sl && oz_ex &&
+                        ozaki_handles(np, pe, K);
+        if (i8) launch_ozaki_split(A, lda, bstride, np, pe, c, K, batch, oz_sl, oz_ex, s, mask);
+        const int upd_prec = prec == GP_MIXED ? GP_FP64 : prec;
+        auto update = [&](int cs, int ce, hipStream_t st) {
+            if (ce <= cs) return;
+            if (i8)
+                launch_syrk_update_i8(A, lda, bstride, np, pe, cs, ce, K, batch, oz_sl, oz_ex, st,
+                                      mask);
+            else
+                launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, batch, st, upd_prec, mask);
+        };
+        const int sp = min(pe + OUTER_NB, np);   // end of the next panel
+        if (sd && cend > sp && sp > pe) {
+            update(pe, sp, s);
+            (void)hipEventRecord(sd->fork, s);
+            (void)hipStreamWaitEvent(sd->s, sd->fork, 0);
+            update(sp, cend, sd->s);
+            (void)hipEventRecord(sd->join, sd->s);
+            pending = true;
+        } else
+            update(pe, cend, s);
     }
+    if (pending) (void)hipStreamWaitEvent(s, sd->join, 0);
 }
 
 void launch_logdet_sum(const double *lpart, int nparts, int batch, double *logdet, hipStream_t s)

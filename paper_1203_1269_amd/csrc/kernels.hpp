@@ -58,15 +58,20 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                   const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
                   int32_t *oz_ex = nullptr);
 
-// GP_MIXED trailing update: digits of the panel rows (OZ_S slices) and one
-// exponent per row, then the INT8-MFMA product.  Returns false (nothing
-// launched) when the shape is not the rank-256 one it handles.
+// GP_MIXED trailing update: digits of the panel rows pe .. np-1 (OZ_S slices)
+// and one exponent per row, then the INT8-MFMA product over the columns
+// [cs, ce) (multiples of 64 from pe).  ozaki_handles() tells whether the
+// shape is the rank-256 one these kernels take.
 #ifndef OZ_S
-#define OZ_S 7
+#define OZ_S GP_MIXED_DIGITS
 #endif
 size_t ozaki_slices_bytes(int np, int batch);
-bool launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
-                           int batch, int8_t *sl, int32_t *ex, hipStream_t s,
+bool ozaki_handles(int np, int pe, int K);
+void launch_ozaki_split(const double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
+                        int batch, int8_t *sl, int32_t *ex, hipStream_t s,
+                        const uint8_t *mask = nullptr);
+void launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, int cs, int ce,
+                           int K, int batch, const int8_t *sl, const int32_t *ex, hipStream_t s,
                            const uint8_t *mask = nullptr);
 
 // a5: iterative refinement of R x = [1 y] with FP64 residuals (R regenerated

@@ -18,9 +18,10 @@
 //     one INT32 accumulator (at most OZ_S K 127^2 < 2^31 for K <= 256), and the
 //     levels are combined in FP64, smallest first, then scaled and subtracted
 //     from the FP64 trailing matrix.
-// With 7 digits the update carries about 49 significant bits relative to the
-// row scales, enough for -2logL to agree with the FP64 path to far below 1e-8
-// relative (a CPU emulation gives 1e-11 .. 1e-13 at n = 1536).
+// With 8 digits the update carries about 56 significant bits relative to the
+// row scales, as many as the FP64 update: -2logL agrees with the FP64 path
+// to far below 1e-8 relative (a CPU emulation of the blocked factorisation
+// gives 1e-10 or less where 7 digits leave up to 6e-9 on ill-conditioned R).
 //
 // v_mfma_i32_16x16x64_i8 layout (measured on gfx950): A[i][k] in lane
 // i + 16 (k / 16), byte k % 16 of the lane's 16 bytes; B[k][j] in lane
@@ -110,10 +111,12 @@ void ozaki_split_kernel(const double *__restrict__ A0, int lda, size_t bstride, 
     }
 }
 
-// 64 x 64 lower tiles of the m x m trailing matrix, four waves of 32 x 32.
-__global__ __launch_bounds__(256, 2)
+// 64 x 64 lower tiles of the m x m trailing matrix in tile columns
+// jt0 .. (rows from the column's diagonal tile down), four waves of 32 x 32.
+__global__ __launch_bounds__(256, 1)
 void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int pe,
-                           int NT, int ntiles, int batch, const int8_t *__restrict__ sl0,
+                           int NT, int jt0, int ntiles, int batch,
+                           const int8_t *__restrict__ sl0,
                            const int32_t *__restrict__ ex0, const uint8_t *__restrict__ mask)
 {
     const int W = ntiles * batch;
@@ -124,7 +127,7 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
     const int b = work / ntiles;
     if (mask && !mask[b]) return;
     int t = work - b * ntiles;
-    int jt = 0;
+    int jt = jt0;
     while (t >= NT - jt) { t -= NT - jt; ++jt; }
     const int it = jt + t;
 
@@ -145,26 +148,37 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
 #pragma unroll
             for (int p = 0; p < 2; ++p) acc[g][q][p] = (int4v){0, 0, 0, 0};
 
-    for (int kc = 0; kc < OZ_KC; ++kc) {
-        int4v fa[OZ_S][2], fb[OZ_S][2];
+    // two fragment buffers: the loads of chunk kc + 1 are issued before the
+    // MFMAs of chunk kc, so their latency hides behind a whole chunk of work
+    int4v fa[2][OZ_S][2], fb[2][OZ_S][2];
+    auto load_chunk = [&](int kc, int buf) {
 #pragma unroll
-        for (int s = 0; s < OZ_S; ++s)
+        for (int sl_t = 0; sl_t < OZ_S; ++sl_t)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const size_t off = (size_t)s * slice_bytes(np) + ((size_t)q * OZ_KC + kc) * 1024;
-                fa[s][q] = *(const int4v *)(fJ + off);
-                fb[s][q] = *(const int4v *)(fI + off);
+                const size_t off =
+                    (size_t)sl_t * slice_bytes(np) + ((size_t)q * OZ_KC + kc) * 1024;
+                fa[buf][sl_t][q] = *(const int4v *)(fJ + off);
+                fb[buf][sl_t][q] = *(const int4v *)(fI + off);
             }
+    };
+    load_chunk(0, 0);
 #pragma unroll
-        for (int s = 0; s < OZ_S; ++s)
+    for (int kc = 0; kc < OZ_KC; ++kc) {
+        const int cur = kc & 1;
+        if (kc + 1 < OZ_KC) load_chunk(kc + 1, cur ^ 1);
+        // keep the scheduler from sinking those loads towards their use
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-            for (int u = 0; u < OZ_S - s; ++u)
+        for (int u = 0; u < OZ_S; ++u)
+#pragma unroll
+            for (int t = 0; t < OZ_S - u; ++t)
 #pragma unroll
                 for (int q = 0; q < 2; ++q)
 #pragma unroll
                     for (int p = 0; p < 2; ++p)
-                        acc[s + u][q][p] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
-                            fa[s][q], fb[u][p], acc[s + u][q][p], 0, 0, 0);
+                        acc[t + u][q][p] = __builtin_amdgcn_mfma_i32_16x16x64_i8(
+                            fa[cur][t][q], fb[cur][u][p], acc[t + u][q][p], 0, 0, 0);
     }
 
     // D[a][b] of block (q, p): column rJ + 16 q + 4 (lane / 16) + e, row rI + 16 p + lane % 16
@@ -199,27 +213,34 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
 
 size_t ozaki_slices_bytes(int np, int batch) { return (size_t)OZ_S * slice_bytes(np) * batch; }
 
-bool launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
-                           int batch, int8_t *sl, int32_t *ex, hipStream_t s, const uint8_t *mask)
+bool ozaki_handles(int np, int pe, int K) { return K == OZ_K && (np - pe) % 64 == 0; }
+
+void launch_ozaki_split(const double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
+                        int batch, int8_t *sl, int32_t *ex, hipStream_t s, const uint8_t *mask)
 {
     const int m = np - pe;
-    if (m <= 0) return true;
-    if (K != OZ_K || (m % 64) != 0) return false;   // caller takes the FP64 update
-    {
-        ProfScope ps(K_OZAKI_SPLIT, 0.0, (8.0 * K + (double)OZ_S * K + 4.0) * m * batch, s);
-        dim3 grid(m / 16, batch);
-        ozaki_split_kernel<<<grid, 256, 0, s>>>(A, lda, bstride, np, pe, kc0, sl, ex, mask);
-    }
-    const int NT = m / 64;
-    const int ntiles = NT * (NT + 1) / 2;
-    const double entries = 0.5 * (double)m * (m + 1);
+    if (m <= 0) return;
+    ProfScope ps(K_OZAKI_SPLIT, 0.0, (8.0 * K + (double)OZ_S * K + 4.0) * m * batch, s);
+    dim3 grid(m / 16, batch);
+    ozaki_split_kernel<<<grid, 256, 0, s>>>(A, lda, bstride, np, pe, kc0, sl, ex, mask);
+}
+
+void launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, int cs, int ce,
+                           int K, int batch, const int8_t *sl, const int32_t *ex, hipStream_t s,
+                           const uint8_t *mask)
+{
+    if (ce <= cs || cs >= np) return;
+    const int NT = (np - pe) / 64;
+    const int jt0 = (cs - pe) / 64, NC = (ce - cs) / 64;
+    int ntiles = 0;
+    for (int jt = jt0; jt < jt0 + NC; ++jt) ntiles += NT - jt;
+    const double entries = (double)(ce - cs) * (np - cs) - 0.5 * (double)(ce - cs) * (ce - cs - 1);
     ProfScope ps(K_SYRK_UPDATE_I8, 2.0 * K * entries * batch,
-                 (16.0 * entries + (double)OZ_S * K * m) * batch, s);
+                 (16.0 * entries + (double)OZ_S * K * (np - cs)) * batch, s);
     const long W = (long)ntiles * batch;
     const long per = (W + NXCD_OZ - 1) / NXCD_OZ;
-    syrk_update_i8_kernel<<<(unsigned)(per * NXCD_OZ), 256, 0, s>>>(A, lda, bstride, np, pe, NT,
-                                                                   ntiles, batch, sl, ex, mask);
-    return true;
+    syrk_update_i8_kernel<<<(unsigned)(per * NXCD_OZ), 256, 0, s>>>(
+        A, lda, bstride, np, pe, NT, jt0, ntiles, batch, sl, ex, mask);
 }
 
 }  // namespace gpk

@@ -65,11 +65,11 @@ def test_workspace_sizing(lib):
     assert lib.gp_workspace_bytes(100, 33, 1, 0) == 0     # d > GP_DMAX
     assert lib.gp_workspace_bytes(100, 2, 0, 0) == 0      # empty batch
     assert lib.gp_workspace_bytes(100, 2, 1, 7) == 0      # unknown precision
-    # the matched-accuracy mixed mode adds 7 digit slices of K = 256 bytes per
+    # the matched-accuracy mixed mode adds 8 digit slices of K = 256 bytes per
     # padded row, one exponent per row and a fallback flag per theta
     mx = binding.workspace_bytes(4096, 8, 128, "mixed")
-    assert mx >= ws + 128 * 4096 * (7 * 256 + 4)
-    assert mx < ws + 128 * 4096 * (7 * 256 + 4) + (1 << 12)
+    assert mx >= ws + 128 * 4096 * (8 * 256 + 4)
+    assert mx < ws + 128 * 4096 * (8 * 256 + 4) + (1 << 12)
     assert binding.workspace_bytes(4096, 8, 128, "mixed_fast") > ws
 
 
