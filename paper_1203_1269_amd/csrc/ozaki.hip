@@ -54,6 +54,15 @@ __host__ __device__ constexpr double level_weight(int g)
 // bytes of one theta's digits for one slice: np rows * K bytes
 __host__ __device__ inline size_t slice_bytes(int np) { return (size_t)np * OZ_K; }
 
+// Byte offset of the 1 KiB fragment (digit t, 16-row block rb, 64-deep k
+// chunk kc) within one theta's digits (nrb = np / 16 row blocks): chunk-major,
+// then row block, then digit, so the digits of consecutive row blocks of one
+// chunk are one contiguous run (32 KiB for the 64 rows of a tile).
+__host__ __device__ inline size_t frag_off(int t, int rb, int kc, int nrb)
+{
+    return (((size_t)kc * nrb + rb) * OZ_S + t) * 1024;
+}
+
 // One workgroup per 16 rows of P: wave w covers k chunk w, lane l row l % 16
 // and k bytes 16 (l / 16) .. + 15 of that chunk.
 __global__ __launch_bounds__(256)
@@ -90,7 +99,7 @@ void ozaki_split_kernel(const double *__restrict__ A0, int lda, size_t bstride, 
     for (int q = 0; q < 16; ++q) v[q] = ldexp(v[q], -e);   // |v| < 1, exact
 
     int8_t *sl = sl0 + (size_t)b * OZ_S * slice_bytes(np);
-    const size_t frag = ((size_t)rb * OZ_KC + wave) * 1024 + (size_t)lane * 16;
+    const size_t frag = (size_t)lane * 16;
 #pragma unroll
     for (int t = 0; t < OZ_S; ++t) {
         int4v w;
@@ -107,7 +116,7 @@ void ozaki_split_kernel(const double *__restrict__ A0, int lda, size_t bstride, 
             }
             w[word] = (int)packed;
         }
-        *(int4v *)(sl + (size_t)t * slice_bytes(np) + frag) = w;
+        *(int4v *)(sl + frag_off(t, rb, wave, np / 16) + frag) = w;
     }
 }
 
@@ -137,8 +146,8 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
     if (rI < rJ) return;                         // strictly upper: nothing to do; no barriers
 
     const int8_t *sl = sl0 + (size_t)b * OZ_S * slice_bytes(np);
-    const int8_t *fI = sl + (size_t)(rI / 16) * OZ_KC * 1024 + (size_t)lane * 16;
-    const int8_t *fJ = sl + (size_t)(rJ / 16) * OZ_KC * 1024 + (size_t)lane * 16;
+    const int8_t *fI = sl + (size_t)lane * 16;
+    const int8_t *fJ = sl + (size_t)lane * 16;
 
     int4v acc[OZ_S][2][2];
 #pragma unroll
@@ -156,17 +165,41 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
         for (int sl_t = 0; sl_t < OZ_S; ++sl_t)
 #pragma unroll
             for (int q = 0; q < 2; ++q) {
-                const size_t off =
-                    (size_t)sl_t * slice_bytes(np) + ((size_t)q * OZ_KC + kc) * 1024;
-                fa[buf][sl_t][q] = *(const int4v *)(fJ + off);
-                fb[buf][sl_t][q] = *(const int4v *)(fI + off);
+                fa[buf][sl_t][q] =
+                    *(const int4v *)(fJ + frag_off(sl_t, rJ / 16 + q, kc, np / 16));
+                fb[buf][sl_t][q] =
+                    *(const int4v *)(fI + frag_off(sl_t, rI / 16 + q, kc, np / 16));
             }
     };
     load_chunk(0, 0);
+    // D[a][b] of block (q, p): column rJ + 16 q + 4 (lane / 16) + e, row rI + 16 p + lane % 16.
+    // The exponents and the C values are fetched while the last chunk's MFMAs
+    // run (the second fragment buffer is free then).
+    const int32_t *ex = ex0 + (size_t)b * np;
+    double *A = A0 + (size_t)b * bstride;
+    int eI[2], eJ[2][4];
+    double cv[2][2][4];
 #pragma unroll
     for (int kc = 0; kc < OZ_KC; ++kc) {
         const int cur = kc & 1;
-        if (kc + 1 < OZ_KC) load_chunk(kc + 1, cur ^ 1);
+        if (kc + 1 < OZ_KC) {
+            load_chunk(kc + 1, cur ^ 1);
+        } else {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) eI[p] = ex[rI + 16 * p + (lane & 15)];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) eJ[q][e] = ex[rJ + 16 * q + 4 * (lane >> 4) + e];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        cv[q][p][e] = A[(size_t)(pe + rI + 16 * p + (lane & 15)) +
+                                        (size_t)(pe + rJ + 16 * q + 4 * (lane >> 4) + e) * lda];
+        }
         // keep the scheduler from sinking those loads towards their use
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -181,17 +214,6 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
                             fa[cur][t][q], fb[cur][u][p], acc[t + u][q][p], 0, 0, 0);
     }
 
-    // D[a][b] of block (q, p): column rJ + 16 q + 4 (lane / 16) + e, row rI + 16 p + lane % 16
-    const int32_t *ex = ex0 + (size_t)b * np;
-    int eI[2], eJ[2][4];
-#pragma unroll
-    for (int p = 0; p < 2; ++p) eI[p] = ex[rI + 16 * p + (lane & 15)];
-#pragma unroll
-    for (int q = 0; q < 2; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) eJ[q][e] = ex[rJ + 16 * q + 4 * (lane >> 4) + e];
-
-    double *A = A0 + (size_t)b * bstride;
 #pragma unroll
     for (int q = 0; q < 2; ++q)
 #pragma unroll
@@ -204,8 +226,7 @@ void syrk_update_i8_kernel(double *__restrict__ A0, int lda, size_t bstride, int
                     v = fma((double)acc[g][q][p][e], level_weight(g), v);
                 const int gi = pe + rI + 16 * p + (lane & 15);
                 const int gj = pe + rJ + 16 * q + 4 * (lane >> 4) + e;
-                double *c = A + (size_t)gi + (size_t)gj * lda;
-                *c -= ldexp(v, eI[p] + eJ[q][e]);
+                A[(size_t)gi + (size_t)gj * lda] = cv[q][p][e] - ldexp(v, eI[p] + eJ[q][e]);
             }
 }
 
