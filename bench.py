@@ -35,8 +35,8 @@ SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
 # --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).
 # Valid only for the kernel and launch loop it was taken on: reported as null
 # once the sha256 of their source differs.
-SYRK_TRAFFIC = {"kernel_sha256": "5d1ce42c1d506d4f0d69b2aa52d1066c54f5538fb69f4b8dd62f218c2a93cfa8",
-                "bytes_per_launch": (2.0 * 4.36e7 + 1.0 * 4.162e7) / 15 * 1024}
+SYRK_TRAFFIC = {"kernel_sha256": "d88baef8ceaeccdd1a2451588df506ecf06996f33c02833db76d3e9927a23747",
+                "bytes_per_launch": (2.0 * 4.8548e7 + 1.0 * 4.1615e7) / 29 * 1024}
 
 
 def syrk_kernel_text():
@@ -275,9 +275,16 @@ def main():
     sy = kstats["syrk_update"]
     achieved = sy["flops"] / (sy["ms"] * 1e-3)
     factor_flops = w.n ** 3 / 3.0
+    # per kernel: event time per step, algorithmic FLOPs and bytes per step,
+    # and the rates they imply (bytes against the 8 TB/s HBM peak); kernels
+    # of the factorisation overlap each other (lookahead), so their event
+    # times include that sharing
     kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
                    "gflop_per_step": v["flops"] / args.steps / 1e9,
-                   "gbyte_per_step": v["bytes"] / args.steps / 1e9}
+                   "gbyte_per_step": v["bytes"] / args.steps / 1e9,
+                   "tflop_per_s": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else None,
+                   "gbyte_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None,
+                   "frac_hbm_peak": v["bytes"] / (v["ms"] * 1e-3) / HBM_PEAK if v["ms"] > 0 else None}
                for k, v in kstats.items()}
     line = {
         "metric": METRIC,
