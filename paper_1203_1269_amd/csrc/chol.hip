@@ -4,14 +4,15 @@
 // library LU instead, Sec. 3).
 //
 // Two-level blocking:
-//   outer panels of OUTER_NB = 256 columns; each is factored by four inner
-//   steps of TB = 64 columns, left-looking inside the panel (update of the
-//   64-column block by the panel's earlier blocks, POTRF of its 64 x 64
-//   diagonal tile, TRSM of the rows below it); then the trailing matrix
-//   receives one right-looking rank-256 update (SYRK/GEMM on FP64 MFMA).
-// The rank-256 trailing update carries ~90% of the n^3/3 flops.  With K = 256
-// each 128 x 128 output tile does 8.4 MFLOP per 256 KiB of C traffic, which
-// keeps it above the FP64 ridge of the chip (78.6 TFLOP/s over 8 TB/s).
+//   outer panels of OUTER_NB = 512 columns (256 for GP_MIXED, whose INT8
+//   update is built for rank 256); each is factored by inner steps of TB = 64
+//   columns, left-looking inside the panel (update of the 64-column block by
+//   the panel's earlier blocks, POTRF of its 64 x 64 diagonal tile, TRSM of
+//   the rows below it); then the trailing matrix receives one right-looking
+//   rank-OUTER_NB update (SYRK/GEMM on FP64 MFMA), which carries most of the
+//   n^3/3 flops.  With K = 512 each 128 x 128 output tile does 16.8 MFLOP per
+//   256 KiB of C traffic, far above the FP64 ridge of the chip (78.6 TFLOP/s
+//   over 8 TB/s); 512 measured 4% faster than 256 and 768 at n = 4096.
 #include <math.h>
 
 #include <map>
@@ -484,10 +485,12 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                   const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex)
 {
     const int nparts = np / TB;
-    SideStream *sd = (bordered || np > 2 * OUTER_NB) ? side_for(s) : nullptr;
+    // the INT8 trailing update is built for rank-256 updates
+    const int nb = prec == GP_MIXED ? 256 : OUTER_NB;
+    SideStream *sd = (bordered || np > 2 * nb) ? side_for(s) : nullptr;
     bool pending = false;   // the side stream holds an update not yet joined
-    for (int c = 0; c < np; c += OUTER_NB) {
-        const int pe = min(c + OUTER_NB, np);
+    for (int c = 0; c < np; c += nb) {
+        const int pe = min(c + nb, np);
         for (int c0 = c; c0 < pe; c0 += TB) {
             // rows that can be nonzero in column block c0: with a border, row
             // np + i is zero left of column i, so rows up to np + c0 + 63
@@ -523,7 +526,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             else
                 launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, batch, st, upd_prec, mask);
         };
-        const int sp = min(pe + OUTER_NB, np);   // end of the next panel
+        const int sp = min(pe + nb, np);   // end of the next panel
         if (sd && cend > sp && sp > pe) {
             update(pe, sp, s);
             (void)hipEventRecord(sd->fork, s);

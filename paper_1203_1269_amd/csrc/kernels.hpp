@@ -15,7 +15,9 @@
 namespace gpk {
 
 constexpr int TB = 64;          // base tile / inner panel width
-constexpr int OUTER_NB = 256;   // outer panel width (K of the trailing update)
+#ifndef OUTER_NB
+#define OUTER_NB 512   // outer panel width (K of the trailing update), FP64 paths
+#endif
 
 inline int pad64(int n) { return (n + TB - 1) / TB * TB; }
 

@@ -147,3 +147,29 @@ def test_repeated_calls_bitwise(gp, prec):
     for k in ("logdet", "mu", "sigma2", "nll", "info"):
         for r in runs[1:]:
             assert np.array_equal(runs[0][k], r[k]), k
+
+
+@pytest.mark.parametrize("prec,floor", [("fp64", 1e-10), ("mixed", MATCH)])
+def test_fullsize_n8192_d10_sampled(gp, prec, floor):
+    """The n=8192, d=10, p=2 workload (32 thetas) in one call per precision:
+    the sampled thetas against the stored oracle values, FP64 at the FP64
+    bar and the mixed mode at the matched bar."""
+    path = os.path.join(HERE, "golden", "mixed_n8192_d10_expected.json")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    exp = json.load(open(path))
+    w = inputs.mixed_at_scale()
+    assert w.X.shape == (8192, 10) and w.B == 32
+    print(f"[parity] fullsize n=8192 d=10 B=32 {prec}", flush=True)
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    got = to_host(gp.nll_batch(ds, w.theta, prec=prec))
+    torch.cuda.empty_cache()
+    assert np.all(got["info"] == 0)
+    sc = scales(w.y)
+    for rec in exp["samples"]:
+        t = rec["index"]
+        for k in ("logdet", "mu", "sigma2", "nll"):
+            r = rec["f80"][k]
+            err = abs(got[k][t] - r) / max(abs(r), sc[k])
+            tol = max(floor, 10 * max(rec["err64"][k], rec["err64_lapack"][k]))
+            assert err <= tol, (t, k, got[k][t], r, err, tol)
