@@ -482,12 +482,12 @@ SideStream *side_for(hipStream_t caller)
 // same operations in the same order per entry as without the lookahead.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
-                  const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex)
+                  const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex, bool lookahead)
 {
     const int nparts = np / TB;
     // the INT8 trailing update is built for rank-256 updates
     const int nb = prec == GP_MIXED ? 256 : OUTER_NB;
-    SideStream *sd = (bordered || np > 2 * nb) ? side_for(s) : nullptr;
+    SideStream *sd = lookahead && (bordered || np > 2 * nb) ? side_for(s) : nullptr;
     bool pending = false;   // the side stream holds an update not yet joined
     for (int c = 0; c < np; c += nb) {
         const int pe = min(c + nb, np);

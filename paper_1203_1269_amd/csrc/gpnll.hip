@@ -97,8 +97,13 @@ size_t gp_workspace_bytes(int32_t n, int32_t d, int32_t batch, int32_t prec)
     return L.total;
 }
 
-gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
-                       void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream)
+}  // extern "C"
+
+namespace gpk {
+
+gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
+                         void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream,
+                         bool lookahead)
 {
     if (!dataset_ok(ds) || batch < 1 || !theta || !out || !ws || !prec_ok(prec))
         return GP_EINVAL;
@@ -118,7 +123,7 @@ gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta,
                       stream);
     double *lk = (double *)(base + L.lk);
     factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, prec, false, nullptr,
-                 (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex));
+                 (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex), lookahead);
     if (prec == GP_FP64) {
         launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
                             stream);
@@ -138,10 +143,21 @@ gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta,
     launch_init(theta, ds->d, batch, info, stream, mask);
     launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
                       stream, mask);
-    factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, GP_FP64, false, mask);
+    factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, GP_FP64, false, mask,
+                 nullptr, nullptr, lookahead);
     launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
                         stream, mask, -1);
     return launched();
+}
+
+}  // namespace gpk
+
+extern "C" {
+
+gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
+                       void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream)
+{
+    return nll_batch_impl(ds, batch, theta, prec, ws, ws_bytes, out, stream, true);
 }
 
 gp_status gp_nll(const gp_dataset *ds, const double *theta, int32_t prec, void *ws,

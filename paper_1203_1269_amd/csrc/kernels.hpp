@@ -58,7 +58,13 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
                   const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
-                  int32_t *oz_ex = nullptr);
+                  int32_t *oz_ex = nullptr, bool lookahead = true);
+
+// gp_nll_batch with the lookahead of the factorisation switchable (the
+// request server runs several calls side by side and turns it off).
+gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
+                         void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream,
+                         bool lookahead);
 
 // GP_MIXED trailing update: digits of the panel rows pe .. np-1 (OZ_S slices)
 // and one exponent per row, then the INT8-MFMA product over the columns

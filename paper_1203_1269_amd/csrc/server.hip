@@ -75,7 +75,8 @@ bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_re
     gp_result *d_out = (gp_result *)(base + out_off);
     (void)hipMemcpyAsync(d_theta, st.h_theta, sizeof(double) * (size_t)B * d.d,
                          hipMemcpyHostToDevice, st.s);
-    gp_status rc = gp_nll_batch(&d, B, d_theta, sv->prec, base, ws_bytes, d_out, st.s);
+    // micro-batches already run side by side: no lookahead stream per call
+    gp_status rc = nll_batch_impl(&d, B, d_theta, sv->prec, base, ws_bytes, d_out, st.s, false);
     (void)hipMemcpyAsync(st.h_out, d_out, sizeof(gp_result) * B, hipMemcpyDeviceToHost, st.s);
     (void)hipEventRecord(st.done, st.s);
     st.busy = true;
