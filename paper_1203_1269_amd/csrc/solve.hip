@@ -1,10 +1,12 @@
 // Forward solves L [a b] = [1 y] and the reductions of eq. 3-4 (paper Sec. 2):
 //   mu = (a.b)/(a.a),  Q = |b - mu a|^2 (two-pass),  sigma2 = Q/n,
 //   nll = log|R| + n ln(sigma2),  log|R| = sum of the per-tile partials.
-// One workgroup per matrix.  The solve is blocked by 64 rows: the 16 waves
-// split the columns left of the block (GEMV with both right-hand sides, each
-// wave reading whole 512-byte column segments of L), then wave 0 finishes the
-// 64 x 64 triangular block with lane-to-lane broadcasts.  The solution
+// One workgroup per matrix.  The solve is blocked by 64 columns and
+// right-looking: wave 0 finishes the 64 x 64 triangular block with
+// lane-to-lane broadcasts, then all 16 waves subtract that block column times
+// its solution from the rows below (both right-hand sides; consecutive
+// threads take consecutive rows, so every column segment of L is read as one
+// contiguous run).  The solution
 // vectors live in LDS (2 n_pad doubles), so n_pad <= 8192.
 // The kernel streams the n^2/2 lower entries of L once: HBM bound.
 #include <math.h>
@@ -17,7 +19,6 @@ namespace {
 
 constexpr int SV_THREADS = 1024;
 constexpr int SV_WAVES = SV_THREADS / 64;
-constexpr int SV_UNROLL = 8;
 
 __device__ __forceinline__ double wave_sum(double v)
 {
@@ -35,7 +36,6 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
 {
     if (mask && !mask[blockIdx.x]) return;
     extern __shared__ double zs[];          // z0[np], z1[np]
-    __shared__ double part[SV_WAVES][2][64];
     __shared__ double red[SV_WAVES][3];
     double *z0 = zs, *z1 = zs + np;
 
@@ -44,37 +44,20 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
     const double *A = A0 + (size_t)b * bstride;
     const int T = np / TB;
 
+    // right-hand sides [1 y] (0 in the padded rows)
+    for (int r = tid; r < np; r += SV_THREADS) {
+        z0[r] = (r < n) ? 1.0 : 0.0;
+        z1[r] = (r < n) ? y[r] : 0.0;
+    }
+    __syncthreads();
     for (int ib = 0; ib < T; ++ib) {
-        const int r = ib * TB + lane;
-        const int ncol = ib * TB;
-        double s0 = 0.0, s1 = 0.0;
-        const double *pr = A + r;
-        int c = wave;
-        for (; c + (SV_UNROLL - 1) * SV_WAVES < ncol; c += SV_UNROLL * SV_WAVES) {
-            double v[SV_UNROLL];
-#pragma unroll
-            for (int u = 0; u < SV_UNROLL; ++u) v[u] = pr[(size_t)(c + u * SV_WAVES) * lda];
-#pragma unroll
-            for (int u = 0; u < SV_UNROLL; ++u) {
-                s0 = fma(v[u], z0[c + u * SV_WAVES], s0);
-                s1 = fma(v[u], z1[c + u * SV_WAVES], s1);
-            }
-        }
-        for (; c < ncol; c += SV_WAVES) {
-            double v = pr[(size_t)c * lda];
-            s0 = fma(v, z0[c], s0);
-            s1 = fma(v, z1[c], s1);
-        }
-        part[wave][0][lane] = s0;
-        part[wave][1][lane] = s1;
-        __syncthreads();
+        const int c0 = ib * TB;
+        // wave 0: triangular solve of the 64 x 64 diagonal block (lane = row)
         if (wave == 0) {
-            double t0 = 0.0, t1 = 0.0;
-            for (int w = 0; w < SV_WAVES; ++w) { t0 += part[w][0][lane]; t1 += part[w][1][lane]; }
-            t0 = ((r < n) ? 1.0 : 0.0) - t0;
-            t1 = ((r < n) ? y[r] : 0.0) - t1;
+            const int r = c0 + lane;
+            double t0 = z0[r], t1 = z1[r];
             double Lrow[TB];
-            const double *pd = A + r + (size_t)ib * TB * lda;
+            const double *pd = A + r + (size_t)c0 * lda;
 #pragma unroll
             for (int j = 0; j < TB; ++j) Lrow[j] = pd[(size_t)j * lda];
 #pragma unroll
@@ -87,6 +70,24 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
             }
             z0[r] = t0;
             z1[r] = t1;
+        }
+        __syncthreads();
+        // all waves: rows below the block lose L(rows, block) z(block); each
+        // column segment of L is read as one contiguous run
+        const int rows = np - c0 - TB;
+        if (rows > 0) {
+            for (int r = c0 + TB + tid; r < np; r += SV_THREADS) {
+                const double *pr = A + r + (size_t)c0 * lda;
+                double s0 = 0.0, s1 = 0.0;
+#pragma unroll 16
+                for (int j = 0; j < TB; ++j) {
+                    const double v = pr[(size_t)j * lda];
+                    s0 = fma(v, z0[c0 + j], s0);
+                    s1 = fma(v, z1[c0 + j], s1);
+                }
+                z0[r] -= s0;
+                z1[r] -= s1;
+            }
         }
         __syncthreads();
     }
