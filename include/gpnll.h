@@ -72,7 +72,7 @@ typedef enum {
                             whose factorisation loses positive definiteness
                             is recomputed on the FP64 path within the same
                             call (gp_result.ir_iters = -1). */
-    GP_MIXED_FAST = 2    /* rank-256 trailing updates on FP32 MFMA with FP32
+    GP_MIXED_FAST = 2    /* rank-512 trailing updates on FP32 MFMA with FP32
                             accumulation; correlation build, diagonal
                             factorisation, TRSM and log-det in FP64; the solves
                             R x = [1 y] are refined with FP64 residuals (R

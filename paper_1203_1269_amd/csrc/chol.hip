@@ -409,7 +409,7 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
     if (ce <= cs || K <= 0) return;
     const double entries = (double)(ce - cs) * np - 0.5 * (double)(cs + ce - 1) * (ce - cs);
     // left-looking updates of one 64-column block inside an outer panel are
-    // reported apart from the rank-256 trailing updates
+    // reported apart from the rank-OUTER_NB trailing updates
     const bool block64 = (ce - cs) == TB;
     const bool f32 = !block64 && prec == GP_MIXED_FAST;
     ProfScope ps(block64 ? K_SYRK_PANEL : (f32 ? K_SYRK_UPDATE_F32 : K_SYRK_UPDATE),

@@ -46,7 +46,7 @@ void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int b
                        const double *lk, hipStream_t s, const uint8_t *mask = nullptr);
 // C(r, c) -= sum_{k in [kc0, kc0+K)} A(r, k) A(c, k) for c in [cs, ce) and
 // r in [c's 128-tile row .. np), i.e. the lower part of the column range.
-// prec selects the arithmetic of rank-256 trailing updates (GP_FP64 or
+// prec selects the arithmetic of the trailing updates (GP_FP64 or
 // GP_MIXED_FAST); updates of a single 64-column block are always FP64.
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce,
                         int kc0, int K, int batch, hipStream_t s, int prec,
