@@ -35,8 +35,8 @@ SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
 # --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).
 # Valid only for the kernel and launch loop it was taken on: reported as null
 # once the sha256 of their source differs.
-SYRK_TRAFFIC = {"kernel_sha256": "d88baef8ceaeccdd1a2451588df506ecf06996f33c02833db76d3e9927a23747",
-                "bytes_per_launch": (2.0 * 4.8548e7 + 1.0 * 4.1615e7) / 29 * 1024}
+SYRK_TRAFFIC = {"kernel_sha256": "42c65b200b09598c0911c878544d3388f04032c28e2ce92015f5fd00d318c3b8",
+                "bytes_per_launch": (2.0 * 3.2933e7 + 1.0 * 1.8809e7) / 13 * 1024}
 
 
 def syrk_kernel_text():

@@ -48,6 +48,7 @@ extern "C" {
 #define GP_NMAX 8192
 #define GP_DMAX 32
 #define GP_MIXED_DIGITS 8   /* digits per panel entry in GP_MIXED */
+#define GP_MIXED_RANK 768   /* rank of the GP_MIXED trailing updates (outer panel width) */
 
 typedef enum {
     GP_OK = 0,
@@ -58,7 +59,7 @@ typedef enum {
 
 typedef enum {
     GP_FP64 = 0,         /* every step in FP64 (FP64 MFMA for the trailing updates) */
-    GP_MIXED = 1,        /* matched accuracy: the rank-256 trailing updates
+    GP_MIXED = 1,        /* matched accuracy: the rank-768 trailing updates
                             C -= P P^T run on INT8 MFMA through an error-free
                             splitting of P (per-row power-of-two scale,
                             GP_MIXED_DIGITS signed 7-bit digits, the digit

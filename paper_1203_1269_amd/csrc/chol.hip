@@ -485,8 +485,8 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                   const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex, bool lookahead)
 {
     const int nparts = np / TB;
-    // the INT8 trailing update is built for rank-256 updates
-    const int nb = prec == GP_MIXED ? 256 : OUTER_NB;
+    // the INT8 trailing update is built for one rank (OZ_RANK)
+    const int nb = prec == GP_MIXED ? OZ_RANK : OUTER_NB;
     SideStream *sd = lookahead && (bordered || np > 2 * nb) ? side_for(s) : nullptr;
     bool pending = false;   // the side stream holds an update not yet joined
     for (int c = 0; c < np; c += nb) {

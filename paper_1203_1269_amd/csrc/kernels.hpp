@@ -73,6 +73,9 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
 #ifndef OZ_S
 #define OZ_S GP_MIXED_DIGITS
 #endif
+#ifndef OZ_RANK
+#define OZ_RANK GP_MIXED_RANK   // rank of the INT8 trailing update = GP_MIXED panel width
+#endif
 size_t ozaki_slices_bytes(int np, int batch);
 bool ozaki_handles(int np, int pe, int K);
 void launch_ozaki_split(const double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,

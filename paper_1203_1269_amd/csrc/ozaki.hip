@@ -15,7 +15,7 @@
 //     exactly in INT32 (|sum| <= K 127^2 per pair);
 //   * only the pairs with t + u < OZ_S are formed (the dropped ones are below
 //     2^(-7 OZ_S) relative to the row scales); pairs with the same t + u share
-//     one INT32 accumulator (at most OZ_S K 127^2 < 2^31 for K <= 256), and the
+//     one INT32 accumulator (at most OZ_S K 127^2 < 2^31 for K <= 2048), and the
 //     levels are combined in FP64, smallest first, then scaled and subtracted
 //     from the FP64 trailing matrix.
 // With 8 digits the update carries about 56 significant bits relative to the
@@ -39,8 +39,11 @@ namespace {
 
 typedef int int4v __attribute__((ext_vector_type(4)));
 
-constexpr int OZ_K = 256;              // update rank handled (outer panel width)
+constexpr int OZ_K = OZ_RANK;          // update rank handled (outer panel width)
 constexpr int OZ_KC = OZ_K / 64;       // 64-deep k chunks per fragment row block
+constexpr int OZ_CPW = OZ_KC / 4;      // chunks per wave in the split kernel
+static_assert(OZ_KC % 4 == 0, "the split kernel gives each of its 4 waves whole chunks");
+static_assert(OZ_S * OZ_K * 127 * 127 < 2147483647, "INT32 level accumulators overflow");
 constexpr int NXCD_OZ = 8;
 
 // 2^(-7 (g + 2)): weight of digit level g (exact)
@@ -63,8 +66,8 @@ __host__ __device__ inline size_t frag_off(int t, int rb, int kc, int nrb)
     return (((size_t)kc * nrb + rb) * OZ_S + t) * 1024;
 }
 
-// One workgroup per 16 rows of P: wave w covers k chunk w, lane l row l % 16
-// and k bytes 16 (l / 16) .. + 15 of that chunk.
+// One workgroup per 16 rows of P: wave w covers k chunks w, w + 4, ...; lane l
+// row l % 16 and k bytes 16 (l / 16) .. + 15 of each of its chunks.
 __global__ __launch_bounds__(256)
 void ozaki_split_kernel(const double *__restrict__ A0, int lda, size_t bstride, int np, int pe,
                         int kc0, int8_t *__restrict__ sl0, int32_t *__restrict__ ex0,
@@ -76,15 +79,17 @@ void ozaki_split_kernel(const double *__restrict__ A0, int lda, size_t bstride, 
     const int rb = blockIdx.x;
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int row = 16 * rb + (lane & 15);           // row of P (0 .. m-1)
-    const int k0 = 64 * wave + 16 * (lane >> 4);     // first k of this lane
-    const double *A = A0 + (size_t)b * bstride + (size_t)(pe + row) + (size_t)(kc0 + k0) * lda;
-    double v[16];
+    const double *A = A0 + (size_t)b * bstride + (size_t)(pe + row) +
+                      (size_t)(kc0 + 64 * wave + 16 * (lane >> 4)) * lda;
+    double v[OZ_CPW][16];
     double m = 0.0;
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-        v[q] = A[(size_t)q * lda];
-        m = fmax(m, fabs(v[q]));
-    }
+    for (int h = 0; h < OZ_CPW; ++h)
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            v[h][q] = A[(size_t)(256 * h + q) * lda];   // chunk wave + 4 h
+            m = fmax(m, fabs(v[h][q]));
+        }
     m = fmax(m, __shfl_xor(m, 16, 64));
     m = fmax(m, __shfl_xor(m, 32, 64));
     if (lane < 16) wmax[wave][lane] = m;
@@ -95,28 +100,30 @@ void ozaki_split_kernel(const double *__restrict__ A0, int lda, size_t bstride, 
     (void)frexp(m, &e);   // m < 2^e (e = 0 for an all-zero row)
     int32_t *ex = ex0 + (size_t)b * np;
     if (wave == 0 && lane < 16) ex[row] = e;
-#pragma unroll
-    for (int q = 0; q < 16; ++q) v[q] = ldexp(v[q], -e);   // |v| < 1, exact
 
-    int8_t *sl = sl0 + (size_t)b * OZ_S * slice_bytes(np);
-    const size_t frag = (size_t)lane * 16;
+    int8_t *sl = sl0 + (size_t)b * OZ_S * slice_bytes(np) + (size_t)lane * 16;
 #pragma unroll
-    for (int t = 0; t < OZ_S; ++t) {
-        int4v w;
+    for (int h = 0; h < OZ_CPW; ++h) {
 #pragma unroll
-        for (int word = 0; word < 4; ++word) {
-            uint32_t packed = 0;
+        for (int q = 0; q < 16; ++q) v[h][q] = ldexp(v[h][q], -e);   // |v| < 1, exact
 #pragma unroll
-            for (int byte = 0; byte < 4; ++byte) {
-                const int q = 4 * word + byte;
-                const double x = v[q] * 128.0;
-                const double dg = trunc(x);      // |dg| <= 127
-                v[q] = x - dg;                   // exact
-                packed |= ((uint32_t)(int)dg & 0xffu) << (8 * byte);
+        for (int t = 0; t < OZ_S; ++t) {
+            int4v w;
+#pragma unroll
+            for (int word = 0; word < 4; ++word) {
+                uint32_t packed = 0;
+#pragma unroll
+                for (int byte = 0; byte < 4; ++byte) {
+                    const int q = 4 * word + byte;
+                    const double x = v[h][q] * 128.0;
+                    const double dg = trunc(x);      // |dg| <= 127
+                    v[h][q] = x - dg;                // exact
+                    packed |= ((uint32_t)(int)dg & 0xffu) << (8 * byte);
+                }
+                w[word] = (int)packed;
             }
-            w[word] = (int)packed;
+            *(int4v *)(sl + frag_off(t, rb, wave + 4 * h, np / 16)) = w;
         }
-        *(int4v *)(sl + frag_off(t, rb, wave, np / 16) + frag) = w;
     }
 }
 

@@ -35,11 +35,11 @@ def gp():
 
 
 @pytest.mark.parametrize("n,d,p,delta,B", [
-    (321, 2, 2.0, 1e-6, 3),      # one update of a 128-row trailing matrix
-    (600, 12, 1.0, 1e-6, 4),     # p = 1
-    (1000, 3, 1.5, 1e-8, 5),     # three updates, small nugget
-    (1500, 8, 1.95, 1e-6, 6),    # general p (pow path)
-    (2048, 6, 2.0, 1e-6, 6),
+    (900, 2, 2.0, 1e-6, 3),      # one INT8 update of a 192-row trailing matrix
+    (600, 12, 1.0, 1e-6, 4),     # p = 1, a single panel (FP64 kernels only)
+    (1000, 3, 1.5, 1e-8, 5),     # one update of 256 rows, small nugget
+    (1500, 8, 1.95, 1e-6, 6),    # general p (pow path), 768-row update
+    (2048, 6, 2.0, 1e-6, 6),     # two updates, ragged last panel
 ])
 def test_mixed_matched_against_oracle(gp, n, d, p, delta, B):
     rng = np.random.default_rng(7000 + n)
