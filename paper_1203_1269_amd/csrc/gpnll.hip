@@ -79,6 +79,7 @@ bool prec_ok(int32_t prec)
 }
 
 bool aligned16(const void *p) { return ((uintptr_t)p & 15) == 0; }
+bool aligned256(const void *p) { return ((uintptr_t)p & 255) == 0; }
 
 gp_status launched()
 {
@@ -107,7 +108,7 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
 {
     if (!dataset_ok(ds) || batch < 1 || !theta || !out || !ws || !prec_ok(prec))
         return GP_EINVAL;
-    if (!aligned16(ws)) return GP_EINVAL;
+    if (!aligned256(ws)) return GP_EINVAL;
     Layout L;
     if (!layout_for(ds->n, batch, L, prec)) return GP_EINVAL;
     if (ws_bytes < L.total) return GP_EWORKSPACE;

@@ -64,3 +64,22 @@ def test_server_rejects_impossible_request(env):
     with pytest.raises(binding.GPError):
         srv.submit([(0, 0, np.ones(ds[0].d))])
     srv.close()
+
+
+def test_server_mixed_matches_alone(env):
+    """The server in the matched-accuracy mixed mode: each result bitwise the
+    one the request gets alone in that mode."""
+    binding, serving, sets, ds = env
+    reqs = inputs.serving_requests(sets, count=120, rate=1e6, seed=44)
+    srv = serving.Server(ds, arena_bytes=2 << 30, max_batch=8, nstreams=4, prec="mixed")
+    lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                         [r[1] for r in reqs], time_limit=120)
+    assert srv.outstanding() == 0 and srv.arena_used() == 0
+    srv.close()
+    for q in range(0, 120, 5):
+        k, th = reqs[q][1], reqs[q][2]
+        r = binding.nll_batch(ds[k], np.asarray(th)[None], prec="mixed")
+        a = {key: v.cpu().numpy()[0] for key, v in r.items()}
+        for key in ("logdet", "mu", "sigma2", "nll"):
+            assert res[q][key] == a[key], (q, key)
+        assert res[q]["info"] == a["info"] == 0
