@@ -71,6 +71,10 @@ def _load():
             f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp,
                           ctypes.c_double, ctypes.c_double, dp, ip, dp, ctypes.c_int]
             f.restype = ctypes.c_int
+            f = getattr(lib, f"orc_predict_{sfx}")
+            f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double,
+                          ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
+            f.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -161,3 +165,27 @@ def rel(x, ref, scale):
     x = np.asarray(x, dtype=np.float64)
     ref = np.asarray(ref, dtype=np.float64)
     return np.abs(x - ref) / np.maximum(np.abs(ref), scale)
+
+
+def predict(X, y, theta, p, delta, Xs, extended: bool = False):
+    """Predictions at the rows of Xs with the model fitted at one theta: the
+    best linear unbiased predictor and its mean squared error (Sec. 3 counts
+    their solves; Sec. 4 scores them by the SSPE).  Returns (mean, mse,
+    OracleResult of the fit for that theta)."""
+    X = _c64(X)
+    n, d = X.shape
+    y = _c64(y).reshape(n)
+    th = _c64(theta).reshape(d)
+    Xs = _c64(Xs).reshape(-1, d)
+    N = Xs.shape[0]
+    fit = np.empty(NOUT)
+    mean = np.empty(N)
+    mse = np.empty(N)
+    info = getattr(_load(), f"orc_predict_{_sfx(extended)}")(
+        n, d, _dp(X), _dp(y), _dp(th), float(p), float(delta), N, _dp(Xs), _dp(fit), _dp(mean),
+        _dp(mse))
+    if info == -100 or info == -101:
+        raise ValueError(f"oracle predict failed ({info})")
+    res = OracleResult(*(np.array([fit[q]]) for q in range(NOUT)),
+                       info=np.array([info], dtype=np.int32))
+    return mean, mse, res

@@ -326,4 +326,75 @@ int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
     return status;
 }
 
+/* Predictions at N test points with the fitted model (Sec. 3: predictions
+ * use one R, one factorisation and back-solves per test point; Sec. 4: the
+ * SSPE over a test set).  The paper does not print the predictor; this is
+ * the best linear unbiased predictor of the model of Sec. 2 and its mean
+ * squared error, written from their definitions with R_delta applied
+ * through forward and back solves:
+ *   r_i(x)  = prod_k exp(-theta_k |x_k - x_ik|^p)        (eq. 2, no nugget)
+ *   mean(x) = mu + r(x)' R^-1 (y - 1 mu)
+ *   mse(x)  = sigma2 (1 - r' R^-1 r + (1 - 1' R^-1 r)^2 / (1' R^-1 1))
+ * with mu, sigma2 of eq. 3.  Xs: N x d row-major.  fit: ORC_NOUT values as
+ * orc_nll_batch.  Returns info as orc_nll_batch (outputs NaN unless 0). */
+int SFX(orc_predict)(int n, int d, const double *X, const double *y, const double *theta_in,
+                     double p_in, double delta_in, int N, const double *Xs, double *fit,
+                     double *mean, double *mse)
+{
+    if (n < 1 || d < 1 || d > 64 || N < 0) return -100;
+    if (!(p_in > 0 && p_in <= 2) || !(delta_in >= 0) || !isfinite(delta_in)) return -100;
+    const REAL p = (REAL)p_in, delta = (REAL)delta_in;
+    size_t nn = (size_t)n * n;
+    REAL *work = (REAL *)malloc(sizeof(REAL) * (2 * nn + 8 * (size_t)n));
+    if (!work) return -101;
+    REAL mu = 0;
+    int info = eval_one(n, d, X, y, theta_in, p, delta, fit, work, &mu);
+    if (info != 0 && info != -1) {
+        for (int j = 0; j < N; ++j) mean[j] = mse[j] = NAN;
+        free(work);
+        return info;
+    }
+    REAL th[64];
+    for (int k = 0; k < d; ++k) th[k] = (REAL)theta_in[k];
+    REAL *L = work + nn;
+    REAL *v = work + 2 * nn, *z = v + n, *alpha = z + n, *u = alpha + n, *r = u + n;
+    REAL *one_inv = r + n;
+    build_corr(n, d, X, th, p, delta, L);
+    cholesky(n, L);
+    /* alpha = R^-1 (y - 1 mu), R^-1 1 */
+    for (int i = 0; i < n; ++i) v[i] = (REAL)y[i] - mu;
+    forward_solve(n, L, v, z);
+    back_solve(n, L, z, alpha);
+    for (int i = 0; i < n; ++i) v[i] = 1;
+    forward_solve(n, L, v, z);
+    back_solve(n, L, z, one_inv);
+    REAL oRo = 0;
+    for (int i = 0; i < n; ++i) oRo += one_inv[i];
+    const REAL sigma2 = (REAL)fit[2];
+    for (int j = 0; j < N; ++j) {
+        for (int i = 0; i < n; ++i) {
+            REAL prod = 1;
+            for (int k = 0; k < d; ++k) {
+                REAL diff = fabs((REAL)Xs[(size_t)j * d + k] - (REAL)X[(size_t)i * d + k]);
+                REAL pw = (diff == 0) ? (REAL)0 : pow(diff, p);
+                prod *= exp(-th[k] * pw);
+            }
+            r[i] = prod;
+        }
+        /* u = R^-1 r by a forward and a back solve */
+        forward_solve(n, L, r, z);
+        back_solve(n, L, z, u);
+        REAL m = mu, rRr = 0, oRr = 0;
+        for (int i = 0; i < n; ++i) {
+            m += r[i] * alpha[i];
+            rRr += r[i] * u[i];
+            oRr += u[i];
+        }
+        mean[j] = (double)m;
+        mse[j] = (double)(sigma2 * (1 - rRr + (1 - oRr) * (1 - oRr) / oRo));
+    }
+    free(work);
+    return info;
+}
+
 int SFX(orc_nout)(void) { return ORC_NOUT; }

@@ -29,6 +29,12 @@ MUTATIONS = [
      "((REAL)n / Q * alpha[i] * alpha[j] + Ri[(size_t)i * n + j]);"),
     ("grad_missing_R", "gk += R[(size_t)i * n + j] * D *", "gk += D *"),
     ("back_solve_transposed", "t -= L[(size_t)m * n + i] * w[m];", "t -= L[(size_t)i * n + m] * w[m];"),
+    ("pred_mse_term_dropped", "mse[j] = (double)(sigma2 * (1 - rRr + (1 - oRr) * (1 - oRr) / oRo));",
+     "mse[j] = (double)(sigma2 * (1 - rRr));"),
+    ("pred_mean_without_mu", "REAL m = mu, rRr = 0, oRr = 0;", "REAL m = 0, rRr = 0, oRr = 0;"),
+    ("pred_cross_power_ignored", "REAL pw = (diff == 0) ? (REAL)0 : pow(diff, p);\n                prod *= exp(-th[k] * pw);",
+     "REAL pw = diff;\n                prod *= exp(-th[k] * pw);"),
+    ("pred_ones_forward_only", "back_solve(n, L, z, one_inv);", "memcpy(one_inv, z, sizeof(REAL) * n);"),
 ]
 
 

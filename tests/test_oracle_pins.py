@@ -380,3 +380,80 @@ def test_paper_tables_fix_the_eq4_convention():
     w = inputs.small_2d(B=4)
     r = oracle.nll_batch(w.X, w.y, w.theta, w.p, w.delta)
     assert np.allclose(r.nll_paper - r.nll, w.n * math.log(w.n), rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# Predictions (Sec. 3: one R, one factorisation, back-solves per test point;
+# Sec. 4: SSPE on a test set).  The predictor is the best linear unbiased one
+# of the model of Sec. 2; its pins come from independent routes.
+
+def _pred_case(seed=21, n=60, d=3, delta=1e-6):
+    rng = np.random.default_rng(seed)
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = np.array([2.0, 1.0, 4.0])[:d]
+    Xs = rng.uniform(size=(25, d))
+    return X, y, th, delta, Xs
+
+
+def test_prediction_interpolates_without_nugget():
+    """delta = 0: the predictor passes through the data and its mean squared
+    error vanishes there."""
+    X, y, th, _, _ = _pred_case()
+    mean, mse, fit = oracle.predict(X, y, th, 2.0, 0.0, X[:12])
+    assert fit.info[0] == 0
+    np.testing.assert_allclose(mean, y[:12], rtol=0, atol=1e-8 * np.std(y))
+    assert np.all(np.abs(mse) <= 1e-9 * fit.sigma2[0])
+
+
+def test_prediction_matches_ordinary_kriging_system():
+    """Independent route: the weights of ordinary kriging from the bordered
+    system [[R, 1], [1', 0]] [lam; m] = [r; 1] (dense solve on the oracle's
+    R) give mean = lam' y and mse = sigma2 (1 - lam' r - m)."""
+    X, y, th, delta, Xs = _pred_case()
+    n = X.shape[0]
+    R = oracle.corr(X, th, 2.0, delta)
+    K = np.zeros((n + 1, n + 1))
+    K[:n, :n] = R
+    K[:n, n] = K[n, :n] = 1.0
+    mean, mse, fit = oracle.predict(X, y, th, 2.0, delta, Xs)
+    s2 = fit.sigma2[0]
+    for j in range(Xs.shape[0]):
+        r = np.exp(-np.sum(th * np.abs(Xs[j] - X) ** 2.0, axis=1))
+        sol = np.linalg.solve(K, np.append(r, 1.0))
+        lam, m = sol[:n], sol[n]
+        assert abs(mean[j] - lam @ y) <= 1e-9 * np.std(y)
+        assert abs(mse[j] - s2 * (1 - lam @ r - m)) <= 1e-9 * s2
+
+
+def test_prediction_far_from_the_data():
+    """r -> 0 far from every design point: mean -> mu, mse -> sigma2 (1 +
+    1 / (1' R^-1 1)), with 1' R^-1 1 from a dense solve."""
+    X, y, th, delta, _ = _pred_case()
+    mean, mse, fit = oracle.predict(X, y, th, 2.0, delta, np.full((2, 3), 50.0))
+    R = oracle.corr(X, th, 2.0, delta)
+    oRo = np.sum(np.linalg.solve(R, np.ones(X.shape[0])))
+    np.testing.assert_allclose(mean, fit.mu[0], rtol=1e-12)
+    np.testing.assert_allclose(mse, fit.sigma2[0] * (1 + 1 / oRo), rtol=1e-9)
+
+
+def test_prediction_invariances():
+    """y -> a y + c moves the mean the same way and scales the mse by a^2; a
+    permutation of the design points changes nothing."""
+    X, y, th, delta, Xs = _pred_case()
+    m0, v0, _ = oracle.predict(X, y, th, 2.0, delta, Xs)
+    m1, v1, _ = oracle.predict(X, 3.0 * y - 2.0, th, 2.0, delta, Xs)
+    np.testing.assert_allclose(m1, 3.0 * m0 - 2.0, rtol=1e-9, atol=1e-9)
+    np.testing.assert_allclose(v1, 9.0 * v0, rtol=1e-8, atol=1e-12)
+    perm = np.random.default_rng(5).permutation(X.shape[0])
+    m2, v2, _ = oracle.predict(X[perm], y[perm], th, 2.0, delta, Xs)
+    np.testing.assert_allclose(m2, m0, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(v2, v0, rtol=1e-8, atol=1e-14)
+
+
+def test_prediction_extended_agrees():
+    X, y, th, delta, Xs = _pred_case()
+    m64, v64, _ = oracle.predict(X, y, th, 1.95, delta, Xs)
+    m80, v80, _ = oracle.predict(X, y, th, 1.95, delta, Xs, extended=True)
+    np.testing.assert_allclose(m64, m80, rtol=1e-10, atol=1e-12)
+    np.testing.assert_allclose(v64, v80, rtol=1e-7, atol=1e-14)
