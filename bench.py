@@ -63,6 +63,7 @@ def parse():
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
     ap.add_argument("--no-large", action="store_true", help="skip the n=8192 leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / L-BFGS leg")
+    ap.add_argument("--no-predict", action="store_true", help="skip the prediction leg")
     ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--serving-arena-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -238,6 +239,52 @@ def gradient_leg(args, dev):
             "lbfgs_batched_calls": int(fit.evaluations), "lbfgs_best_nll": float(np.min(fit.nll))}
 
 
+def prediction_leg(args, dev):
+    """Fit + predict at a 1000-point test set (n=4096, d=8, 8 thetas in one
+    call), with the SSPE of each fitted theta against the noiseless response;
+    the same thetas through gp_nll_batch alone for the cost of the fit."""
+    import numpy as np
+    import torch
+    from paper_1203_1269_amd import binding, inputs
+    w = inputs.prediction_workload()
+    ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
+    theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
+    Xs = torch.as_tensor(w.Xs, dtype=torch.float64, device=dev).contiguous()
+    B, N = w.theta.shape[0], w.Xs.shape[0]
+    ws = binding.alloc_workspace(binding.predict_workspace_bytes(ds.n, ds.d, B, N), dev)
+    binding.predict(ds, theta, Xs, ws)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    binding.profile_begin(max_launches=4000 * steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        fit, mean, mse = binding.predict(ds, theta, Xs, ws)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    kst = binding.profile_end()
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        binding.nll_batch(ds, theta, ws=ws)
+    torch.cuda.synchronize()
+    dfit = (time.perf_counter() - t1) / steps
+    sspe = ((mean.cpu().numpy() - w.ys[None, :]) ** 2).sum(axis=1)
+    nll = fit["nll"].cpu().numpy()
+    best = int(np.nanargmin(nll))
+    del ws
+    torch.cuda.empty_cache()
+    return {"workload": "pred_n4096_d8", "n": ds.n, "d": ds.d, "batch": B, "test_points": N,
+            "p": w.p, "delta": w.delta, "ms_per_call": dt * 1e3,
+            "predictions_per_s": B * N / dt, "fits_with_prediction_per_s": B / dt,
+            "ms_fit_alone": dfit * 1e3,
+            "sspe_best_nll_theta": float(sspe[best]), "sspe_median": float(np.median(sspe)),
+            "mse_mean_best_nll_theta": float(mse[best].mean().item()),
+            "kernels": {k: {"ms_per_call": v["ms"] / steps,
+                            "gbyte_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9,
+                            "tflop_per_s": v["flops"] / (v["ms"] * 1e-3) / 1e12}
+                        for k, v in kst.items() if v["ms"] > 0}}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -316,6 +363,8 @@ def main():
         line["large_n8192"] = large_leg(args, dev)
     if not args.no_grad:
         line["gradient"] = gradient_leg(args, dev)
+    if not args.no_predict:
+        line["prediction"] = prediction_leg(args, dev)
     if not args.no_serving:
         line["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:

@@ -39,7 +39,9 @@
  *   - Matrices are column-major.  Internally the order is padded to
  *     n_pad = 64 * ceil(n / 64) with an identity block, which changes neither
  *     the determinant nor the solves.
- *   - Limits: 2 <= n <= GP_NMAX, 1 <= d <= GP_DMAX, 0 < p <= 2, delta >= 0.
+ *   - Limits: 2 <= n <= GP_NMAX, 1 <= d <= GP_DMAX, 0 < p <= 2, delta >= 0,
+ *     1 <= batch <= GP_BATCH_MAX (larger batches are rejected with GP_EINVAL;
+ *     split them over several calls).
  */
 #ifndef GPNLL_H
 #define GPNLL_H
@@ -54,6 +56,7 @@ extern "C" {
 
 #define GP_NMAX 8192
 #define GP_DMAX 32
+#define GP_BATCH_MAX 65535
 #define GP_MIXED_DIGITS 8   /* digits per panel entry in GP_MIXED */
 #define GP_MIXED_RANK 768   /* rank of the GP_MIXED trailing updates (outer panel width) */
 
@@ -176,6 +179,26 @@ size_t gp_grad_workspace_bytes(int32_t n, int32_t d, int32_t batch);
 gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta,
                       int32_t prec, void *ws, size_t ws_bytes, gp_result *out,
                       double *grad, hipStream_t stream);
+
+/* Predictions at N test points with the model fitted at each of `batch`
+ * thetas (the paper obtains them with one R, one Cholesky factorisation and
+ * back-solves per test point, Sec. 3, and scores them by the sum of squared
+ * prediction errors over a test set, Sec. 4).  The paper does not print the
+ * predictor; this is the best linear unbiased one of the model of Sec. 2 and
+ * its mean squared error:
+ *     mean(x) = mu + r(x)' R^-1 (y - 1 mu)
+ *     mse(x)  = sigma2 (1 - r' R^-1 r + (1 - 1' R^-1 r)^2 / (1' R^-1 1))
+ * with r_i(x) = exp(-sum_k theta_k |x_k - x_ik|^p) (eq. 2, no nugget) and mu,
+ * sigma2 of eq. 3.  FP64 throughout (prec must be GP_FP64).
+ * Xstar: device, N x d row-major test points (may be NULL when N == 0).
+ * fit: device, batch results as gp_nll_batch.  mean, mse: device, batch x N
+ * (NaN where the fit's info is > 0 or -3).  ws: at least
+ * gp_predict_workspace_bytes(n, d, batch, N) bytes ((n_pad + 64 +
+ * 64 ceil(N/64)) x n_pad doubles per theta plus O(n)), 256-byte aligned. */
+size_t gp_predict_workspace_bytes(int32_t n, int32_t d, int32_t batch, int32_t N);
+gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
+                     const double *Xstar, int32_t N, int32_t prec, void *ws, size_t ws_bytes,
+                     gp_result *fit, double *mean, double *mse, hipStream_t stream);
 
 /* ------------------------------------------------------------------------ */
 /* Continuous-batching request server (host API over gp_nll_batch).

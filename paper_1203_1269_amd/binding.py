@@ -79,6 +79,11 @@ def lib():
         L.gp_grad_workspace_bytes.restype = sz
         L.gp_nll_grad.argtypes = [ctypes.POINTER(GPDataset), i32, vp, i32, vp, sz, vp, vp, vp]
         L.gp_nll_grad.restype = ctypes.c_int
+        L.gp_predict_workspace_bytes.argtypes = [i32, i32, i32, i32]
+        L.gp_predict_workspace_bytes.restype = sz
+        L.gp_predict.argtypes = [ctypes.POINTER(GPDataset), i32, vp, vp, i32, i32, vp, sz, vp, vp,
+                                 vp, vp]
+        L.gp_predict.restype = ctypes.c_int
         L.gp_profile_begin.argtypes = [i32]
         L.gp_profile_begin.restype = ctypes.c_int
         L.gp_profile_end.argtypes = [ctypes.POINTER(GPKernelStat), i32]
@@ -215,8 +220,8 @@ def profile_begin(max_launches: int = 100000) -> None:
 def profile_end() -> dict:
     """Stop timing; returns {kernel: {launches, ms, flops, bytes}} (waits for
     the recorded events)."""
-    stats = (GPKernelStat * 16)()
-    m = lib().gp_profile_end(stats, 16)
+    stats = (GPKernelStat * 32)()
+    m = lib().gp_profile_end(stats, 32)
     if m < 0:
         _check(m, "gp_profile_end")
     return {stats[q].name.decode(): {"launches": stats[q].launches, "ms": stats[q].ms,
@@ -226,6 +231,33 @@ def profile_end() -> dict:
 
 def grad_workspace_bytes(n: int, d: int, batch: int) -> int:
     return int(lib().gp_grad_workspace_bytes(n, d, batch))
+
+
+def predict_workspace_bytes(n: int, d: int, batch: int, N: int) -> int:
+    return int(lib().gp_predict_workspace_bytes(n, d, batch, N))
+
+
+def predict(ds: Dataset, theta, Xstar, ws: torch.Tensor | None = None):
+    """Predictions (mean and mean squared error) at the rows of Xstar (N x d)
+    with the model fitted at each row of theta (B x d).  Returns (fit results
+    dict as nll_batch, mean B x N, mse B x N), device tensors."""
+    th = _dev_f64(theta, ds.device).reshape(-1, ds.d)
+    Xs = _dev_f64(Xstar, ds.device).reshape(-1, ds.d)
+    B, N = th.shape[0], Xs.shape[0]
+    need = predict_workspace_bytes(ds.n, ds.d, B, N)
+    if need == 0:
+        raise GPError("gp_predict_workspace_bytes rejected the sizes")
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, ds.device)
+    fit = torch.empty((B, 5), dtype=torch.float64, device=ds.device)
+    mean = torch.empty((B, N), dtype=torch.float64, device=ds.device)
+    mse = torch.empty((B, N), dtype=torch.float64, device=ds.device)
+    st = lib().gp_predict(ds.c, B, ctypes.c_void_p(th.data_ptr()), ctypes.c_void_p(Xs.data_ptr()),
+                          N, PRECISIONS["fp64"], ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                          ctypes.c_void_p(fit.data_ptr()), ctypes.c_void_p(mean.data_ptr()),
+                          ctypes.c_void_p(mse.data_ptr()), _stream_ptr())
+    _check(st, "gp_predict")
+    return unpack_results(fit), mean, mse
 
 
 def nll_grad(ds: Dataset, theta, ws: torch.Tensor | None = None):

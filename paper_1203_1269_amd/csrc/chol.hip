@@ -482,7 +482,8 @@ SideStream *side_for(hipStream_t caller)
 // same operations in the same order per entry as without the lookahead.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
-                  const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex, bool lookahead)
+                  const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex, bool lookahead,
+                  int extra)
 {
     const int nparts = np / TB;
     // the INT8 trailing update is built for one rank (OZ_RANK)
@@ -494,7 +495,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
         for (int c0 = c; c0 < pe; c0 += TB) {
             // rows that can be nonzero in column block c0: with a border, row
             // np + i is zero left of column i, so rows up to np + c0 + 63
-            const int rmax = bordered ? np + c0 + TB : np;
+            const int rmax = bordered ? np + c0 + TB : np + extra;
             // left-looking inside the outer panel: bring block c0 up to date
             // with the blocks [c, c0) of the same panel, then factor it
             if (c0 > c)
@@ -506,7 +507,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
         // right-looking rank-(pe - c) update of the trailing matrix: rows up
         // to rlim, columns [pe, cend); with a border it also covers the
         // border columns np .. np + pe - 1
-        const int rlim = bordered ? np + pe : np;
+        const int rlim = bordered ? np + pe : np + extra;
         const int cend = bordered ? np + pe : np;
         if (cend <= pe) continue;
         if (pending) {
@@ -514,7 +515,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             pending = false;
         }
         const int K = pe - c;
-        const bool i8 = prec == GP_MIXED && !bordered && oz_sl && oz_ex &&
+        const bool i8 = prec == GP_MIXED && !bordered && extra == 0 && oz_sl && oz_ex &&
                         ozaki_handles(np, pe, K);
         if (i8) launch_ozaki_split(A, lda, bstride, np, pe, c, K, batch, oz_sl, oz_ex, s, mask);
         const int upd_prec = prec == GP_MIXED ? GP_FP64 : prec;

@@ -31,7 +31,7 @@ struct Layout {
 
 bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
 {
-    if (n < 2 || n > GP_NMAX || batch < 1) return false;
+    if (n < 2 || n > GP_NMAX || batch < 1 || batch > GP_BATCH_MAX) return false;
     L.np = pad64(n);
     L.bstride = (size_t)L.np * L.np;
     size_t off = 0;
@@ -61,6 +61,34 @@ bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
         off += 3 * vec + align_up((size_t)batch);
     }
     L.total = off;
+    return true;
+}
+
+// Predictions: the matrix carries 64 + 64 ceil(N / 64) extra rows below it
+// ([1 y] and the test points' cross-correlations).
+struct PredLayout {
+    int np, extra, lda;
+    size_t mat, bstride, lpart, info, lk, total;
+};
+
+bool pred_layout_for(int n, int batch, int N, PredLayout &P)
+{
+    if (n < 2 || n > GP_NMAX || batch < 1 || batch > GP_BATCH_MAX || N < 0 || N > (1 << 20))
+        return false;
+    P.np = pad64(n);
+    P.extra = TB + pad64(N);
+    P.lda = P.np + P.extra;
+    P.bstride = (size_t)P.lda * P.np;
+    size_t off = 0;
+    P.mat = off;
+    off = align_up(off + P.bstride * sizeof(double) * batch);
+    P.lpart = off;
+    off = align_up(off + sizeof(double) * (size_t)(P.np / TB) * batch);
+    P.info = off;
+    off = align_up(off + sizeof(int32_t) * (size_t)batch);
+    P.lk = off;
+    off = align_up(off + sizeof(double) * TB * TB * (size_t)batch);
+    P.total = off;
     return true;
 }
 
@@ -106,7 +134,8 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
                          void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream,
                          bool lookahead)
 {
-    if (!dataset_ok(ds) || batch < 1 || !theta || !out || !ws || !prec_ok(prec))
+    if (!dataset_ok(ds) || batch < 1 || batch > GP_BATCH_MAX || !theta || !out || !ws ||
+        !prec_ok(prec))
         return GP_EINVAL;
     if (!aligned256(ws)) return GP_EINVAL;
     Layout L;
@@ -170,7 +199,8 @@ gp_status gp_nll(const gp_dataset *ds, const double *theta, int32_t prec, void *
 gp_status gp_corr_build(const gp_dataset *ds, int32_t batch, const double *theta, double *R,
                         int32_t ldr, int32_t *info, hipStream_t stream)
 {
-    if (!dataset_ok(ds) || batch < 1 || !theta || !R || !info) return GP_EINVAL;
+    if (!dataset_ok(ds) || batch < 1 || batch > GP_BATCH_MAX || !theta || !R || !info)
+        return GP_EINVAL;
     const int np = pad64(ds->n);
     if (ldr < np) return GP_EINVAL;
     launch_init(theta, ds->d, batch, info, stream);
@@ -181,7 +211,7 @@ gp_status gp_corr_build(const gp_dataset *ds, int32_t batch, const double *theta
 
 size_t gp_cholesky_ws_bytes(int32_t n, int32_t batch)
 {
-    if (n < 1 || n > GP_NMAX || batch < 1) return 0;
+    if (n < 1 || n > GP_NMAX || batch < 1 || batch > GP_BATCH_MAX) return 0;
     return align_up(sizeof(double) * (size_t)(pad64(n) / TB) * batch) +
            align_up(sizeof(double) * TB * TB * (size_t)batch);
 }
@@ -189,7 +219,9 @@ size_t gp_cholesky_ws_bytes(int32_t n, int32_t batch)
 gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda, int32_t *info,
                             double *logdet, void *ws, size_t ws_bytes, hipStream_t stream)
 {
-    if (n < 1 || n > GP_NMAX || batch < 1 || !A || !info || !logdet || !ws) return GP_EINVAL;
+    if (n < 1 || n > GP_NMAX || batch < 1 || batch > GP_BATCH_MAX || !A || !info || !logdet ||
+        !ws)
+        return GP_EINVAL;
     const int np = pad64(n);
     if (lda < np || !aligned16(A) || (lda % 2) != 0) return GP_EINVAL;
     if (ws_bytes < gp_cholesky_ws_bytes(n, batch)) return GP_EWORKSPACE;
@@ -209,7 +241,8 @@ struct GradLayout {
 
 static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
 {
-    if (n < 2 || n > GP_NMAX || batch < 1 || d < 1 || d > GP_DMAX) return false;
+    if (n < 2 || n > GP_NMAX || batch < 1 || batch > GP_BATCH_MAX || d < 1 || d > GP_DMAX)
+        return false;
     L.np = pad64(n);
     const int T = L.np / TB;
     L.ntiles = T * (T + 1) / 2;
@@ -232,6 +265,42 @@ static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
     return true;
 }
 
+size_t gp_predict_workspace_bytes(int32_t n, int32_t d, int32_t batch, int32_t N)
+{
+    PredLayout P;
+    if (d < 1 || d > GP_DMAX || !pred_layout_for(n, batch, N, P)) return 0;
+    return P.total;
+}
+
+gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
+                     const double *Xstar, int32_t N, int32_t prec, void *ws, size_t ws_bytes,
+                     gp_result *fit, double *mean, double *mse, hipStream_t stream)
+{
+    if (!dataset_ok(ds) || batch < 1 || batch > GP_BATCH_MAX || !theta || !fit || !ws ||
+        prec != GP_FP64 || N < 0)
+        return GP_EINVAL;
+    if (N > 0 && (!Xstar || !mean || !mse)) return GP_EINVAL;
+    if (!aligned256(ws)) return GP_EINVAL;
+    PredLayout P;
+    if (!pred_layout_for(ds->n, batch, N, P)) return GP_EINVAL;
+    if (ws_bytes < P.total) return GP_EWORKSPACE;
+    char *base = (char *)ws;
+    double *A = (double *)(base + P.mat);
+    double *lpart = (double *)(base + P.lpart);
+    int32_t *info = (int32_t *)(base + P.info);
+    const int np = P.np;
+    launch_init(theta, ds->d, batch, info, stream);
+    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, P.lda, P.bstride,
+                      np, stream);
+    launch_pred_rows(A, P.lda, P.bstride, np, ds->X, ds->n, ds->d, ds->p, ds->y, theta, Xstar, N,
+                     P.extra, batch, stream);
+    factor_batch(A, P.lda, P.bstride, np, batch, info, lpart, (double *)(base + P.lk), stream,
+                 GP_FP64, false, nullptr, nullptr, nullptr, true, P.extra);
+    launch_pred_reduce(A, P.lda, P.bstride, np, ds->n, lpart, np / TB, info, N, batch, fit, mean,
+                       mse, stream);
+    return launched();
+}
+
 size_t gp_grad_workspace_bytes(int32_t n, int32_t d, int32_t batch)
 {
     GradLayout L;
@@ -242,7 +311,8 @@ size_t gp_grad_workspace_bytes(int32_t n, int32_t d, int32_t batch)
 gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
                       void *ws, size_t ws_bytes, gp_result *out, double *grad, hipStream_t stream)
 {
-    if (!dataset_ok(ds) || batch < 1 || !theta || !out || !grad || !ws || prec != GP_FP64)
+    if (!dataset_ok(ds) || batch < 1 || batch > GP_BATCH_MAX || !theta || !out || !grad || !ws ||
+        prec != GP_FP64)
         return GP_EINVAL;
     if (!aligned16(ws)) return GP_EINVAL;
     GradLayout L;

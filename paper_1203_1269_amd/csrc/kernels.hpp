@@ -58,7 +58,25 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
                   const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
-                  int32_t *oz_ex = nullptr, bool lookahead = true);
+                  int32_t *oz_ex = nullptr, bool lookahead = true, int extra = 0);
+
+// Predictions: rows np .. np + extra - 1 below the n_pad x n_pad matrix ride
+// through the factorisation as rows below the diagonal (factor_batch with
+// `extra`), so each is turned into its forward solve L^-1 v:
+//   row np:       1 (c < n), 0 otherwise        -> a = L^-1 1
+//   row np + 1:   y_c                            -> b = L^-1 y
+//   rows np + 2 .. np + 63: zero
+//   row np + 64 + j: r_c(x*_j) = exp(-sum_k theta_k |x*_jk - x_ck|^p) (c < n)
+//                                                -> w_j = L^-1 r(x*_j)
+// (leading dimension np + extra, extra = 64 + 64 ceil(N / 64)).
+void launch_pred_rows(double *A, int lda, size_t bstride, int np, const double *X, int n, int d,
+                      double p, const double *y, const double *theta, const double *Xs, int N,
+                      int extra, int batch, hipStream_t s);
+// fit (as gp_result) from rows a, b; then per test point
+//   mean = mu + w.(b - mu a),  mse = sigma2 (1 - w.w + (1 - a.w)^2 / a.a)
+void launch_pred_reduce(const double *A, int lda, size_t bstride, int np, int n,
+                        const double *lpart, int nparts, const int32_t *info, int N, int batch,
+                        gp_result *fit, double *mean, double *mse, hipStream_t s);
 
 // gp_nll_batch with the lookahead of the factorisation switchable (the
 // request server runs several calls side by side and turns it off).

@@ -25,6 +25,8 @@ enum KernelKind {
     K_SOLVE2,
     K_OZAKI_SPLIT,
     K_SYRK_UPDATE_I8,
+    K_PRED_ROWS,
+    K_PRED_REDUCE,
     K_NUM_KINDS
 };
 

@@ -99,6 +99,32 @@ def gradient_workload(seed: int = 5, n: int = 4096, B: int = 16) -> Workload:
 
 
 @dataclass
+class PredictionWorkload:
+    X: np.ndarray
+    y: np.ndarray
+    theta: np.ndarray
+    p: float
+    delta: float
+    Xs: np.ndarray        # test points
+    ys: np.ndarray        # noiseless response at the test points
+
+
+def prediction_workload(seed: int = 8, n: int = 4096, d: int = 8, B: int = 8, N: int = 1000,
+                        p: float = 1.95, delta: float = 1e-6) -> PredictionWorkload:
+    """Training data as the n=4096, d=8 workload (LHS-like design, sine
+    response with noise 0.01), an N-point LHS-like test set with the same
+    response function without noise, and B theta in [0.05, 20]^d."""
+    rng = np.random.default_rng(seed)
+    X = lhs_design(n, d, rng)
+    w = rng.uniform(0.5, 2.0, d)
+    y = np.sin(np.pi * X) @ w + 0.01 * rng.standard_normal(n)
+    Xs = lhs_design(N, d, rng)
+    ys = np.sin(np.pi * Xs) @ w
+    th = log_uniform_theta(B, d, 0.05, 20.0, rng)
+    return PredictionWorkload(X, y, th, p, delta, Xs, ys)
+
+
+@dataclass
 class ServingDataset:
     X: np.ndarray
     y: np.ndarray

@@ -4,6 +4,7 @@ Calls only the CPU oracle (80-bit and FP64 builds, plus LAPACK on the
 oracle's R to measure the FP64 rounding spread) on the seeded inputs of
 paper_1203_1269_amd.inputs; the GPU path is not involved.  Usage:
     python tests/golden/make_expected.py fp64_n4096_d8
+    python tests/golden/make_expected.py pred_n4096_d8 2
 """
 import json
 import os
@@ -20,7 +21,7 @@ import oracle  # noqa: E402
 from paper_1203_1269_amd import inputs  # noqa: E402
 
 sys.path.insert(0, os.path.dirname(HERE))
-from parity_util import lapack_fp64  # noqa: E402
+from parity_util import lapack_fp64, lapack_predict  # noqa: E402
 
 WORKLOADS = {
     "fp64_n4096_d8": inputs.fp64_at_scale,
@@ -58,9 +59,38 @@ def main_grad(name, k=2):
     print(path, out["oracle_seconds"])
 
 
+def main_pred(name, k=2, points=16):
+    """Oracle predictions (80-bit and FP64 builds, plus the LAPACK predictor)
+    at `points` evenly spaced test points for k sampled thetas of the
+    prediction workload."""
+    w = inputs.prediction_workload()
+    idx = sample_indices(w.theta, k)
+    pts = np.unique(np.linspace(0, w.Xs.shape[0] - 1, points).astype(int))
+    Xs = w.Xs[pts]
+    t0 = time.time()
+    samples = []
+    for t in idx:
+        m80, v80, f80 = oracle.predict(w.X, w.y, w.theta[t], w.p, w.delta, Xs, extended=True)
+        m64, v64, _ = oracle.predict(w.X, w.y, w.theta[t], w.p, w.delta, Xs)
+        ml, vl = lapack_predict(w.X, w.y, w.theta[t], w.p, w.delta, Xs)
+        samples.append({"index": int(t), "theta": w.theta[t].tolist(), "points": pts.tolist(),
+                        "sigma2_f80": float(f80.sigma2[0]), "mean_f80": m80.tolist(),
+                        "mse_f80": v80.tolist(), "mean_f64": m64.tolist(),
+                        "mse_f64": v64.tolist(), "mean_lapack": ml.tolist(),
+                        "mse_lapack": vl.tolist()})
+    out = {"workload": name, "n": w.X.shape[0], "d": w.X.shape[1], "B": w.theta.shape[0],
+           "N": w.Xs.shape[0], "p": w.p, "delta": w.delta, "samples": samples,
+           "oracle_seconds": time.time() - t0}
+    path = os.path.join(HERE, f"{name}_expected.json")
+    json.dump(out, open(path, "w"), indent=1)
+    print(path, out["oracle_seconds"])
+
+
 def main(name, k=4):
     if name.startswith("grad_"):
         return main_grad(name, k)
+    if name.startswith("pred_"):
+        return main_pred(name, k)
     w = WORKLOADS[name]()
     idx = sample_indices(w.theta, k)
     t0 = time.time()

@@ -76,3 +76,36 @@ def compare(gpu: dict, r80, tol: dict, y, label=""):
 
 def to_host(res: dict) -> dict:
     return {k: v.cpu().numpy() for k, v in res.items()}
+
+
+def lapack_predict(X, y, theta, p, delta, Xs):
+    """A second, independent FP64 predictor for one theta (LAPACK Cholesky
+    of the oracle's R, cho_solve, the cross-correlations from the oracle's
+    correlation of the stacked points): mean and mse at the rows of Xs.  Used
+    only to measure the FP64 rounding spread of the predictions."""
+    n = X.shape[0]
+    R = oracle.corr(X, theta, p, delta)
+    cf = sla.cho_factor(R, lower=True)
+    one = np.ones(n)
+    Ri1 = sla.cho_solve(cf, one)
+    mu = (Ri1 @ y) / (one @ Ri1)
+    res = y - mu
+    a = sla.cho_solve(cf, res)
+    sigma2 = res @ a / n
+    # cross-correlations without the nugget: the off-diagonal block of R of
+    # the stacked points [X; Xs]
+    full = oracle.corr(np.vstack([X, Xs]), theta, p, 0.0)
+    r = full[:n, n:]
+    u = sla.cho_solve(cf, r)
+    mean = mu + r.T @ a
+    mse = sigma2 * (1.0 - np.sum(r * u, axis=0) + (1.0 - one @ u) ** 2 / (one @ Ri1))
+    return mean, mse
+
+
+def pred_tolerance(m64, v64, m80, v80, mlap, vlap, sd_y, sigma2, floor=FP64_TOL):
+    """Per-point tolerances of mean (scale sd(y)) and mse (scale sigma2):
+    max(floor, SLACK * the larger distance of the two FP64 codes from the
+    80-bit values)."""
+    em = np.fmax(np.abs(m64 - m80), np.abs(mlap - m80)) / np.maximum(np.abs(m80), sd_y)
+    ev = np.fmax(np.abs(v64 - v80), np.abs(vlap - v80)) / np.maximum(np.abs(v80), sigma2)
+    return np.maximum(floor, SLACK * em), np.maximum(floor, SLACK * ev)

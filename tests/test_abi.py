@@ -75,6 +75,20 @@ def test_workspace_sizing(lib):
     assert mx >= ws + 128 * 4096 * (S * K + 4)
     assert mx < ws + 128 * 4096 * (S * K + 4) + (1 << 12)
     assert binding.workspace_bytes(4096, 8, 128, "mixed_fast") > ws
+    bmax = binding.header_constant("GP_BATCH_MAX")
+    assert lib.gp_workspace_bytes(100, 2, bmax, 0) > 0
+    assert lib.gp_workspace_bytes(100, 2, bmax + 1, 0) == 0
+    assert lib.gp_grad_workspace_bytes(100, 2, bmax + 1) == 0
+    assert lib.gp_cholesky_ws_bytes(100, bmax + 1) == 0
+    # predictions: 64 + 64 ceil(N / 64) extra rows below each matrix
+    pw = binding.predict_workspace_bytes(4096, 8, 8, 1000)
+    rows = 4096 + 64 + 1024
+    assert 8 * rows * 4096 * 8 <= pw < 8 * rows * 4096 * 8 + (1 << 20)
+    assert binding.predict_workspace_bytes(4096, 8, 8, 0) > 0
+    assert binding.predict_workspace_bytes(4096, 8, 8, -1) == 0
+    assert binding.predict_workspace_bytes(4096, 8, 8, (1 << 20) + 1) == 0
+    assert binding.predict_workspace_bytes(4096, 33, 8, 10) == 0
+    assert binding.predict_workspace_bytes(100, 2, bmax + 1, 10) == 0
 
 
 def _ds(X=1 << 20, y=1 << 21, n=100, d=2, p=2.0, delta=1e-6):
@@ -113,6 +127,26 @@ def test_invalid_call_arguments_rejected_on_host(lib):
     assert lib.gp_cholesky_batch(100, 2, vp(1 << 22), 129, vp(1 << 23), vp(1 << 24), vp(1 << 25), 1 << 20, None) == binding.GP_EINVAL  # odd lda
     assert lib.gp_cholesky_batch(100, 2, vp(1 << 22), 128, vp(1 << 23), vp(1 << 24), vp(1 << 25), 0, None) == binding.GP_EWORKSPACE
     assert lib.gp_corr_build(ctypes.byref(ds), 4, vp(1 << 22), vp(1 << 23), 100, vp(1 << 24), None) == binding.GP_EINVAL  # ldr < 128
+    assert lib.gp_nll_batch(ctypes.byref(ds), 65536, vp(1 << 22), 0, vp(1 << 23), 1 << 40, vp(1 << 24), None) == binding.GP_EINVAL  # batch > GP_BATCH_MAX
+    # prediction entry point: FP64 only, test points and outputs needed when N > 0
+    pneed = lib.gp_predict_workspace_bytes(100, 2, 4, 10)
+    args = [ctypes.byref(ds), 4, vp(1 << 22), vp(1 << 21), 10, 0, vp(1 << 23), pneed, vp(1 << 24),
+            vp(1 << 25), vp(1 << 26), None]
+
+    def pred(**chg):
+        a = list(args)
+        for i, v in chg.items():
+            a[int(i[1:])] = v
+        return lib.gp_predict(*a)
+    assert pred(a5=1) == binding.GP_EINVAL                     # not FP64
+    assert pred(a3=None) == binding.GP_EINVAL                  # no test points
+    assert pred(a9=None) == binding.GP_EINVAL                  # no mean
+    assert pred(a10=None) == binding.GP_EINVAL                 # no mse
+    assert pred(a8=None) == binding.GP_EINVAL                  # no fit
+    assert pred(a4=-1) == binding.GP_EINVAL                    # N < 0
+    assert pred(a6=vp((1 << 23) + 8)) == binding.GP_EINVAL     # unaligned workspace
+    assert pred(a7=pneed - 1) == binding.GP_EWORKSPACE
+    assert pred(a1=0) == binding.GP_EINVAL
 
 
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
