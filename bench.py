@@ -35,8 +35,8 @@ SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
 # --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).
 # Valid only for the kernel and launch loop it was taken on: reported as null
 # once the sha256 of their source differs.
-SYRK_TRAFFIC = {"kernel_sha256": "42c65b200b09598c0911c878544d3388f04032c28e2ce92015f5fd00d318c3b8",
-                "bytes_per_launch": (2.0 * 3.2933e7 + 1.0 * 1.8809e7) / 13 * 1024}
+SYRK_TRAFFIC = {"kernel_sha256": "35655bdfc8f3a5ca5e59ae8d81d0aa397130d0967e25838186a8b7afdf1e42ea",
+                "bytes_per_launch": (2.0 * 3.3547e7 + 1.0 * 1.8809e7) / 13 * 1024}
 
 
 def syrk_kernel_text():
@@ -86,6 +86,40 @@ def cpu_baseline(w, threads):
     return {"value": len(th) / dt, "unit": "evals/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(th)} of the {w.B} thetas of the same n={w.n}, d={w.d} workload, "
                       f"one theta per thread, {dt:.1f} s wall"}
+
+
+def cpu_lapack_baseline(w, threads, count=16):
+    """Second CPU baseline: NumPy for R and SciPy/LAPACK (multi-threaded
+    OpenBLAS on `threads` threads) for the Cholesky and the solves, one theta
+    at a time; the theta-independent power terms are computed once for the
+    sample and their time is included."""
+    import numpy as np
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_limits
+    th = w.theta[:count]
+    n = w.n
+    with threadpool_limits(limits=threads):
+        t0 = time.perf_counter()
+        D = np.empty((w.d, n, n))
+        for k in range(w.d):
+            np.power(np.abs(w.X[:, k, None] - w.X[None, :, k]), w.p, out=D[k])
+        one = np.ones(n)
+        nll = np.empty(len(th))
+        for t in range(len(th)):
+            R = np.exp(-np.tensordot(th[t], D, axes=1))
+            R[np.diag_indices(n)] += w.delta
+            L = sla.cholesky(R, lower=True, overwrite_a=True, check_finite=False)
+            ab = sla.solve_triangular(L, np.stack([one, w.y], axis=1), lower=True,
+                                      check_finite=False)
+            a, b = ab[:, 0], ab[:, 1]
+            mu = a @ b / (a @ a)
+            Q = np.sum((b - mu * a) ** 2)
+            nll[t] = 2 * np.sum(np.log(np.diag(L))) + n * np.log(Q / n)
+        dt = time.perf_counter() - t0
+    assert np.all(np.isfinite(nll))
+    return {"value": len(th) / dt, "unit": "evals/s", "cores": threads, "kind": "lapack",
+            "sample": f"{len(th)} of the {w.B} thetas of the same n={w.n}, d={w.d} workload, "
+                      f"one theta at a time on {threads} BLAS threads, {dt:.1f} s wall"}
 
 
 def syrk_traffic():
@@ -370,6 +404,7 @@ def main():
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
         line["cpu_baseline"] = cpu_baseline(w, threads)
+        line["cpu_lapack"] = cpu_lapack_baseline(w, threads)
     print(json.dumps(line), flush=True)
 
 
