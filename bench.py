@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-large", action="store_true", help="skip the n=8192 leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / L-BFGS leg")
     ap.add_argument("--no-predict", action="store_true", help="skip the prediction leg")
+    ap.add_argument("--no-ga", action="store_true", help="skip the GA whole-fit leg")
     ap.add_argument("--serving-requests", type=int, default=5000)
     ap.add_argument("--serving-arena-gb", type=float, default=16.0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -319,6 +320,56 @@ def prediction_leg(args, dev):
                         for k, v in kst.items() if v["ms"] > 0}}
 
 
+# whole-fit wall times (s) the paper reports (10-replication averages; the
+# CPU n=4064 fit ran once): Table 1 (d=2) and Table 2 (d=6), CPU and CUDA
+PAPER_FIT_SECONDS = {
+    (16, 2): (0.91, 2.26), (32, 2): (3.30, 4.94), (64, 2): (12.90, 5.50),
+    (128, 2): (51.45, 7.25), (256, 2): (206.18, 9.88), (512, 2): (911.93, 20.75),
+    (64, 6): (32.32, 9.45), (256, 6): (514.43, 16.58), (1024, 6): (13325.86, 96.19),
+    (4064, 6): (161925.05, 1059.71),
+}
+
+
+def ga_leg(args, dev, reps=3):
+    """Whole GP fits at the shapes of the paper's two examples: a genetic
+    algorithm with population 100 over 20 generations (2000 -2logL
+    evaluations, one gp_nll_batch call per generation), then prediction at a
+    1000-point test set with the best theta; p = 1.95, no nugget, synthetic
+    LHS-like designs with a noiseless sine response, `reps` replications."""
+    import numpy as np
+    import torch
+    from paper_1203_1269_amd import binding, ga, inputs
+    out = {}
+    warm = inputs.ga_workload(64, 2, seed=99)
+    ga.fit_ga(binding.Dataset(warm.X, warm.y, warm.p, warm.delta, device=dev), seed=0)
+    for (n, d), (cpu_s, cuda_s) in PAPER_FIT_SECONDS.items():
+        secs, nll, sspe, infeasible = [], [], [], []
+        for r in range(reps):
+            w = inputs.ga_workload(n, d, seed=1000 * d + n + r)
+            ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
+            Xs = torch.as_tensor(w.Xs, dtype=torch.float64, device=dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fit = ga.fit_ga(ds, seed=r, keep_history=True)
+            _, mean, _ = binding.predict(ds, fit.theta[None, :], Xs)
+            m = mean[0].cpu().numpy()
+            secs.append(time.perf_counter() - t0)
+            nll.append(fit.nll)
+            sspe.append(float(((m - w.ys) ** 2).sum()))
+            infeasible.append(int(sum(int(np.isinf(v).sum()) for v in fit.all_values)))
+            del ds, Xs
+        t = float(np.mean(secs))
+        out[f"n{n}_d{d}"] = {
+            "fit_seconds": t, "evals_per_s": 2000 / t, "best_nll_mean": float(np.mean(nll)),
+            "best_nll_plus_n_ln_n_mean": float(np.mean(nll) + n * np.log(n)),
+            "sspe_median": float(np.median(sspe)),
+            "failed_evaluations_mean": float(np.mean(infeasible)),
+            "paper_cpu_fit_seconds": cpu_s, "paper_cuda_fit_seconds": cuda_s,
+            "ratio_vs_paper_cuda_fit": cuda_s / t}
+    torch.cuda.empty_cache()
+    return {"replications": reps, "population": 100, "generations": 20, "fits": out}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -399,6 +450,8 @@ def main():
         line["gradient"] = gradient_leg(args, dev)
     if not args.no_predict:
         line["prediction"] = prediction_leg(args, dev)
+    if not args.no_ga:
+        line["ga_fit"] = ga_leg(args, dev)
     if not args.no_serving:
         line["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:

@@ -124,6 +124,21 @@ def prediction_workload(seed: int = 8, n: int = 4096, d: int = 8, B: int = 8, N:
     return PredictionWorkload(X, y, th, p, delta, Xs, ys)
 
 
+def ga_workload(n: int, d: int, seed: int, N: int = 1000, p: float = 1.95,
+                delta: float = 0.0) -> PredictionWorkload:
+    """A fit at the shapes of the paper's examples (d = 2 or 6, n up to
+    4064, p = 1.95, no nugget, a deterministic response): LHS-like design,
+    sine response without noise, an N-point LHS-like test set with its
+    response.  theta is left empty (the GA chooses it)."""
+    rng = np.random.default_rng(seed)
+    X = lhs_design(n, d, rng)
+    w = rng.uniform(0.5, 2.0, d)
+    y = np.sin(np.pi * X) @ w
+    Xs = lhs_design(N, d, rng)
+    ys = np.sin(np.pi * Xs) @ w
+    return PredictionWorkload(X, y, np.empty((0, d)), p, delta, Xs, ys)
+
+
 @dataclass
 class ServingDataset:
     X: np.ndarray
