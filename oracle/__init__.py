@@ -58,21 +58,23 @@ def _load():
         ip = ctypes.POINTER(ctypes.c_int32)
         for sfx in ("f64", "f80"):
             f = getattr(lib, f"orc_corr_{sfx}")
-            f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_double, dp]
+            f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int,
+                          ctypes.c_double, dp]
             f.restype = ctypes.c_int
             f = getattr(lib, f"orc_cholesky_{sfx}")
             f.argtypes = [ctypes.c_int, dp, dp]
             f.restype = ctypes.c_int
             f = getattr(lib, f"orc_nll_batch_{sfx}")
             f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp,
-                          ctypes.c_double, ctypes.c_double, dp, ip, ctypes.c_int]
+                          ctypes.c_double, ctypes.c_int, ctypes.c_double, dp, ip, ctypes.c_int]
             f.restype = ctypes.c_int
             f = getattr(lib, f"orc_grad_batch_{sfx}")
             f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int, dp,
-                          ctypes.c_double, ctypes.c_double, dp, ip, dp, ctypes.c_int]
+                          ctypes.c_double, ctypes.c_int, ctypes.c_double, dp, ip, dp,
+                          ctypes.c_int]
             f.restype = ctypes.c_int
             f = getattr(lib, f"orc_predict_{sfx}")
-            f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double,
+            f.argtypes = [ctypes.c_int, ctypes.c_int, dp, dp, dp, ctypes.c_double, ctypes.c_int,
                           ctypes.c_double, ctypes.c_int, dp, dp, dp, dp]
             f.restype = ctypes.c_int
         _lib = lib
@@ -91,6 +93,18 @@ def _sfx(extended: bool) -> str:
     return "f80" if extended else "f64"
 
 
+# correlation families: the power exponential of eq. (2) (exponent p) and
+# the Matern families with smoothness 3/2 and 5/2 that Sec. 2 names as the
+# alternative (p is not used by them)
+FAMILIES = {"powexp": 0, "matern32": 1, "matern52": 2}
+
+
+def _fam(family: str) -> int:
+    if family not in FAMILIES:
+        raise ValueError(f"unknown correlation family {family!r}")
+    return FAMILIES[family]
+
+
 @dataclass
 class OracleResult:
     logdet: np.ndarray
@@ -104,13 +118,15 @@ class OracleResult:
     info: np.ndarray
 
 
-def corr(X, theta, p, delta, extended: bool = False) -> np.ndarray:
-    """R_delta of eq. (2) plus the nugget (Sec. 2): full symmetric n x n."""
+def corr(X, theta, p, delta, extended: bool = False, family: str = "powexp") -> np.ndarray:
+    """R_delta of eq. (2) (or a Matern family) plus the nugget (Sec. 2):
+    full symmetric n x n."""
     X = _c64(X)
     n, d = X.shape
     th = _c64(theta).reshape(d)
     R = np.empty((n, n))
-    st = getattr(_load(), f"orc_corr_{_sfx(extended)}")(n, d, _dp(X), _dp(th), float(p), float(delta), _dp(R))
+    st = getattr(_load(), f"orc_corr_{_sfx(extended)}")(n, d, _dp(X), _dp(th), float(p),
+                                                        _fam(family), float(delta), _dp(R))
     if st != 0:
         raise ValueError(f"oracle corr failed ({st})")
     return R
@@ -125,7 +141,8 @@ def cholesky(A, extended: bool = False):
     return L, int(info)
 
 
-def nll_batch(X, y, theta, p, delta, extended: bool = False, nthreads: int = 0) -> OracleResult:
+def nll_batch(X, y, theta, p, delta, extended: bool = False, nthreads: int = 0,
+              family: str = "powexp") -> OracleResult:
     """Profile likelihood, eq. (3)-(4), for each row of theta (B x d)."""
     X = _c64(X)
     n, d = X.shape
@@ -135,14 +152,15 @@ def nll_batch(X, y, theta, p, delta, extended: bool = False, nthreads: int = 0) 
     out = np.empty((B, NOUT))
     info = np.empty(B, dtype=np.int32)
     st = getattr(_load(), f"orc_nll_batch_{_sfx(extended)}")(
-        n, d, _dp(X), _dp(y), B, _dp(th), float(p), float(delta), _dp(out),
+        n, d, _dp(X), _dp(y), B, _dp(th), float(p), _fam(family), float(delta), _dp(out),
         info.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), int(nthreads))
     if st != 0:
         raise ValueError(f"oracle nll_batch failed ({st})")
     return OracleResult(*(out[:, q].copy() for q in range(NOUT)), info=info)
 
 
-def grad_batch(X, y, theta, p, delta, extended: bool = False, nthreads: int = 0):
+def grad_batch(X, y, theta, p, delta, extended: bool = False, nthreads: int = 0,
+               family: str = "powexp"):
     """Gradient of nll w.r.t. theta (adjoint formula; see gp_oracle.c)."""
     X = _c64(X)
     n, d = X.shape
@@ -153,7 +171,7 @@ def grad_batch(X, y, theta, p, delta, extended: bool = False, nthreads: int = 0)
     info = np.empty(B, dtype=np.int32)
     g = np.empty((B, d))
     st = getattr(_load(), f"orc_grad_batch_{_sfx(extended)}")(
-        n, d, _dp(X), _dp(y), B, _dp(th), float(p), float(delta), _dp(out),
+        n, d, _dp(X), _dp(y), B, _dp(th), float(p), _fam(family), float(delta), _dp(out),
         info.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _dp(g), int(nthreads))
     if st != 0:
         raise ValueError(f"oracle grad_batch failed ({st})")
@@ -167,7 +185,7 @@ def rel(x, ref, scale):
     return np.abs(x - ref) / np.maximum(np.abs(ref), scale)
 
 
-def predict(X, y, theta, p, delta, Xs, extended: bool = False):
+def predict(X, y, theta, p, delta, Xs, extended: bool = False, family: str = "powexp"):
     """Predictions at the rows of Xs with the model fitted at one theta: the
     best linear unbiased predictor and its mean squared error (Sec. 3 counts
     their solves; Sec. 4 scores them by the SSPE).  Returns (mean, mse,
@@ -182,8 +200,8 @@ def predict(X, y, theta, p, delta, Xs, extended: bool = False):
     mean = np.empty(N)
     mse = np.empty(N)
     info = getattr(_load(), f"orc_predict_{_sfx(extended)}")(
-        n, d, _dp(X), _dp(y), _dp(th), float(p), float(delta), N, _dp(Xs), _dp(fit), _dp(mean),
-        _dp(mse))
+        n, d, _dp(X), _dp(y), _dp(th), float(p), _fam(family), float(delta), N, _dp(Xs),
+        _dp(fit), _dp(mean), _dp(mse))
     if info == -100 or info == -101:
         raise ValueError(f"oracle predict failed ({info})")
     res = OracleResult(*(np.array([fit[q]]) for q in range(NOUT)),

@@ -11,6 +11,8 @@
  * Graphics Processing Units" (arXiv 1203.1269):
  *   - model y(x_i) = mu + z(x_i)                          (Sec. 2, eq. 1)
  *   - power-exponential correlation, product form       (Sec. 2, eq. 2)
+ *   - Matern correlation (smoothness 3/2 and 5/2), the alternative that
+ *     Sec. 2 names, in the same product-over-dimensions form
  *   - closed-form mu_hat and sigma_hat^2                  (Sec. 2, eq. 3)
  *   - profile likelihood -2 log L                         (Sec. 2, eq. 4)
  *   - determinant and solves through a Cholesky factor   (Sec. 2, text after
@@ -51,10 +53,55 @@
 /* Output record per theta: logdet, mu, sigma2, nll, nll_paper, Q, aa, ab. */
 #define ORC_NOUT 8
 
-/* eq. 2 written literally as a product over dimensions of exponentials,
- * plus the nugget on the diagonal.  Full symmetric n x n, row-major. */
+/* Correlation families (fam):
+ *   0  power exponential, eq. 2: exp(-theta_k |x_ik - x_jk|^p)
+ *   1  Matern, smoothness 3/2:  (1 + sqrt(3) h) exp(-sqrt(3) h)
+ *   2  Matern, smoothness 5/2:  (1 + sqrt(5) h + 5 h^2 / 3) exp(-sqrt(5) h)
+ * with h = theta_k |x_ik - x_jk| for the Matern families (the half-integer
+ * closed forms of 2^(1-nu) / Gamma(nu) (sqrt(2 nu) h)^nu K_nu(sqrt(2 nu) h));
+ * every family is a product of such factors over the d dimensions. */
+static REAL corr_factor(int fam, REAL diff, REAL th, REAL p)
+{
+    if (fam == 0) {
+        REAL pw = (diff == 0) ? (REAL)0 : pow(diff, p);
+        return exp(-th * pw);
+    }
+    REAL h = th * diff;
+    if (fam == 1) {
+        REAL c = sqrt((REAL)3);
+        return (1 + c * h) * exp(-c * h);
+    }
+    REAL c = sqrt((REAL)5);
+    return (1 + c * h + c * c * h * h / 3) * exp(-c * h);
+}
+
+/* -d ln(factor) / d theta_k:
+ *   fam 0: |x_ik - x_jk|^p
+ *   fam 1: diff * 3 h / (1 + sqrt(3) h)
+ *   fam 2: diff * 5 h (1 + sqrt(5) h) / (3 (1 + sqrt(5) h + 5 h^2 / 3)) */
+static REAL corr_dlog(int fam, REAL diff, REAL th, REAL p)
+{
+    if (fam == 0) return (diff == 0) ? (REAL)0 : pow(diff, p);
+    REAL h = th * diff;
+    if (fam == 1) {
+        REAL c = sqrt((REAL)3);
+        return diff * c * c * h / (1 + c * h);
+    }
+    REAL c = sqrt((REAL)5);
+    return diff * c * c * h * (1 + c * h) / (3 * (1 + c * h + c * c * h * h / 3));
+}
+
+static int family_ok(int fam, double p)
+{
+    if (fam == 0) return p > 0 && p <= 2;
+    return fam == 1 || fam == 2;
+}
+
+/* eq. 2 (or a Matern family) written literally as a product over dimensions
+ * of per-dimension factors, plus the nugget on the diagonal.  Full
+ * symmetric n x n, row-major. */
 static void build_corr(int n, int d, const double *X, const REAL *theta,
-                       REAL p, REAL delta, REAL *R)
+                       REAL p, int fam, REAL delta, REAL *R)
 {
     for (int i = 0; i < n; ++i) {
         R[(size_t)i * n + i] = (REAL)1 + delta;
@@ -62,8 +109,7 @@ static void build_corr(int n, int d, const double *X, const REAL *theta,
             REAL prod = 1;
             for (int k = 0; k < d; ++k) {
                 REAL diff = fabs((REAL)X[(size_t)i * d + k] - (REAL)X[(size_t)j * d + k]);
-                REAL pw = (diff == 0) ? (REAL)0 : pow(diff, p);
-                prod *= exp(-theta[k] * pw);
+                prod *= corr_factor(fam, diff, theta[k], p);
             }
             R[(size_t)i * n + j] = prod;
             R[(size_t)j * n + i] = prod;
@@ -134,7 +180,7 @@ static void fill_nan(double *out)
  * REALs.  Steps follow Sec. 2: build R (eq. 2), factor it, log|R| from the
  * factor, a = L^-1 1 and b = L^-1 y, then eq. 3 and eq. 4. */
 static int eval_one(int n, int d, const double *X, const double *y,
-                    const double *theta_in, REAL p, REAL delta,
+                    const double *theta_in, REAL p, int fam, REAL delta,
                     double *out, REAL *work, REAL *mu_out)
 {
     if (!theta_ok(d, theta_in)) { fill_nan(out); return -3; }
@@ -146,7 +192,7 @@ static int eval_one(int n, int d, const double *X, const double *y,
     REAL *a = yv + n;
     REAL *b = a + n;
 
-    build_corr(n, d, X, theta, p, delta, A);
+    build_corr(n, d, X, theta, p, fam, delta, A);
     int info = cholesky(n, A);
     if (info != 0) { fill_nan(out); return info; }
 
@@ -191,14 +237,14 @@ static int eval_one(int n, int d, const double *X, const double *y,
 
 /* R_delta for one theta, full symmetric, row-major, written as double. */
 int SFX(orc_corr)(int n, int d, const double *X, const double *theta,
-                  double p, double delta, double *R_out)
+                  double p, int fam, double delta, double *R_out)
 {
-    if (n < 1 || d < 1 || d > 64) return -100;
+    if (n < 1 || d < 1 || d > 64 || !family_ok(fam, p)) return -100;
     REAL th[64];
     for (int k = 0; k < d; ++k) th[k] = (REAL)theta[k];
     REAL *R = (REAL *)malloc(sizeof(REAL) * (size_t)n * n);
     if (!R) return -101;
-    build_corr(n, d, X, th, (REAL)p, (REAL)delta, R);
+    build_corr(n, d, X, th, (REAL)p, fam, (REAL)delta, R);
     for (size_t q = 0; q < (size_t)n * n; ++q) R_out[q] = (double)R[q];
     free(R);
     return 0;
@@ -220,11 +266,11 @@ int SFX(orc_cholesky)(int n, const double *A_in, double *L_out)
  * info: B.  nthreads <= 0 uses the OpenMP default. Returns -100 on invalid
  * sizes/scalars, else 0. */
 int SFX(orc_nll_batch)(int n, int d, const double *X, const double *y,
-                       int B, const double *theta, double p, double delta,
+                       int B, const double *theta, double p, int fam, double delta,
                        double *out, int32_t *info, int nthreads)
 {
     if (n < 1 || d < 1 || d > 64 || B < 0) return -100;
-    if (!(p > 0 && p <= 2) || !(delta >= 0) || !isfinite(delta)) return -100;
+    if (!family_ok(fam, p) || !(delta >= 0) || !isfinite(delta)) return -100;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #else
@@ -240,7 +286,7 @@ int SFX(orc_nll_batch)(int n, int d, const double *X, const double *y,
         } else {
 #pragma omp for schedule(dynamic, 1)
             for (int t = 0; t < B; ++t)
-                info[t] = eval_one(n, d, X, y, theta + (size_t)t * d, (REAL)p,
+                info[t] = eval_one(n, d, X, y, theta + (size_t)t * d, (REAL)p, fam,
                                    (REAL)delta, out + (size_t)t * ORC_NOUT, work, NULL);
             free(work);
         }
@@ -250,16 +296,17 @@ int SFX(orc_nll_batch)(int n, int d, const double *X, const double *y,
 
 /* Gradient of nll = log|R| + n ln(sigma2) with respect to theta.
  * d nll / d theta_k = tr(R^-1 dR_k) - n * alpha' dR_k alpha / Q, with
- * alpha = R^-1 (y - 1 mu), dR_k,ij = -R_ij |x_ik - x_jk|^p (i != j).
+ * alpha = R^-1 (y - 1 mu), dR_k,ij = -R_ij G_k,ij (i != j) with
+ * G_k,ij = -d ln(factor_k) / d theta_k (|x_ik - x_jk|^p for eq. 2).
  * The mu derivative drops out because 1' alpha = 0 at mu = mu_hat.
  * R^-1 is formed column by column from the Cholesky factor (n forward and
  * back solves).  grad: B x d.  Also fills `out` like orc_nll_batch. */
 int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
-                        int B, const double *theta, double p, double delta,
+                        int B, const double *theta, double p, int fam, double delta,
                         double *out, int32_t *info, double *grad, int nthreads)
 {
     if (n < 1 || d < 1 || d > 64 || B < 0) return -100;
-    if (!(p > 0 && p <= 2) || !(delta >= 0) || !isfinite(delta)) return -100;
+    if (!family_ok(fam, p) || !(delta >= 0) || !isfinite(delta)) return -100;
 #ifdef _OPENMP
     if (nthreads <= 0) nthreads = omp_get_max_threads();
 #else
@@ -285,7 +332,7 @@ int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
                 REAL *v = work + 3 * nn;
                 REAL *z = v + n, *w = z + n, *alpha = w + n;
                 REAL mu = 0;
-                int inf = eval_one(n, d, X, y, th_in, (REAL)p, (REAL)delta, o, work, &mu);
+                int inf = eval_one(n, d, X, y, th_in, (REAL)p, fam, (REAL)delta, o, work, &mu);
                 info[t] = inf;
                 if (inf != 0) {
                     for (int k = 0; k < d; ++k) g[k] = NAN;
@@ -293,7 +340,7 @@ int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
                 }
                 REAL th[64];
                 for (int k = 0; k < d; ++k) th[k] = (REAL)th_in[k];
-                build_corr(n, d, X, th, (REAL)p, (REAL)delta, R);
+                build_corr(n, d, X, th, (REAL)p, fam, (REAL)delta, R);
                 memcpy(L, R, sizeof(REAL) * nn);
                 cholesky(n, L);
                 for (int c = 0; c < n; ++c) {
@@ -313,8 +360,8 @@ int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
                         for (int j = 0; j < n; ++j) {
                             if (i == j) continue;
                             REAL diff = fabs((REAL)X[(size_t)i * d + k] - (REAL)X[(size_t)j * d + k]);
-                            REAL D = (diff == 0) ? (REAL)0 : pow(diff, (REAL)p);
-                            gk += R[(size_t)i * n + j] * D *
+                            REAL G = corr_dlog(fam, diff, th[k], (REAL)p);
+                            gk += R[(size_t)i * n + j] * G *
                                   ((REAL)n / Q * alpha[i] * alpha[j] - Ri[(size_t)i * n + j]);
                         }
                     g[k] = (double)gk;
@@ -332,23 +379,23 @@ int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
  * the best linear unbiased predictor of the model of Sec. 2 and its mean
  * squared error, written from their definitions with R_delta applied
  * through forward and back solves:
- *   r_i(x)  = prod_k exp(-theta_k |x_k - x_ik|^p)        (eq. 2, no nugget)
+ *   r_i(x)  = prod_k factor_k(|x_k - x_ik|)              (eq. 2, no nugget)
  *   mean(x) = mu + r(x)' R^-1 (y - 1 mu)
  *   mse(x)  = sigma2 (1 - r' R^-1 r + (1 - 1' R^-1 r)^2 / (1' R^-1 1))
  * with mu, sigma2 of eq. 3.  Xs: N x d row-major.  fit: ORC_NOUT values as
  * orc_nll_batch.  Returns info as orc_nll_batch (outputs NaN unless 0). */
 int SFX(orc_predict)(int n, int d, const double *X, const double *y, const double *theta_in,
-                     double p_in, double delta_in, int N, const double *Xs, double *fit,
-                     double *mean, double *mse)
+                     double p_in, int fam, double delta_in, int N, const double *Xs,
+                     double *fit, double *mean, double *mse)
 {
     if (n < 1 || d < 1 || d > 64 || N < 0) return -100;
-    if (!(p_in > 0 && p_in <= 2) || !(delta_in >= 0) || !isfinite(delta_in)) return -100;
+    if (!family_ok(fam, p_in) || !(delta_in >= 0) || !isfinite(delta_in)) return -100;
     const REAL p = (REAL)p_in, delta = (REAL)delta_in;
     size_t nn = (size_t)n * n;
     REAL *work = (REAL *)malloc(sizeof(REAL) * (2 * nn + 8 * (size_t)n));
     if (!work) return -101;
     REAL mu = 0;
-    int info = eval_one(n, d, X, y, theta_in, p, delta, fit, work, &mu);
+    int info = eval_one(n, d, X, y, theta_in, p, fam, delta, fit, work, &mu);
     if (info != 0 && info != -1) {
         for (int j = 0; j < N; ++j) mean[j] = mse[j] = NAN;
         free(work);
@@ -359,7 +406,7 @@ int SFX(orc_predict)(int n, int d, const double *X, const double *y, const doubl
     REAL *L = work + nn;
     REAL *v = work + 2 * nn, *z = v + n, *alpha = z + n, *u = alpha + n, *r = u + n;
     REAL *one_inv = r + n;
-    build_corr(n, d, X, th, p, delta, L);
+    build_corr(n, d, X, th, p, fam, delta, L);
     cholesky(n, L);
     /* alpha = R^-1 (y - 1 mu), R^-1 1 */
     for (int i = 0; i < n; ++i) v[i] = (REAL)y[i] - mu;
@@ -376,8 +423,7 @@ int SFX(orc_predict)(int n, int d, const double *X, const double *y, const doubl
             REAL prod = 1;
             for (int k = 0; k < d; ++k) {
                 REAL diff = fabs((REAL)Xs[(size_t)j * d + k] - (REAL)X[(size_t)i * d + k]);
-                REAL pw = (diff == 0) ? (REAL)0 : pow(diff, p);
-                prod *= exp(-th[k] * pw);
+                prod *= corr_factor(fam, diff, th[k], p);
             }
             r[i] = prod;
         }

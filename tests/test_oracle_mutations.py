@@ -13,9 +13,11 @@ SRC = os.path.join(ROOT, "oracle", "gp_oracle.c")
 MUTATIONS = [
     ("nugget_dropped", "R[(size_t)i * n + i] = (REAL)1 + delta;", "R[(size_t)i * n + i] = (REAL)1;"),
     ("power_ignored", "pow(diff, p)", "(diff * diff)"),
-    ("theta_index", "prod *= exp(-theta[k] * pw);", "prod *= exp(-theta[0] * pw);"),
-    ("x_index_transposed", "fabs((REAL)X[(size_t)i * d + k] - (REAL)X[(size_t)j * d + k]);\n                REAL pw",
-     "fabs((REAL)X[(size_t)k * d + i % d] - (REAL)X[(size_t)j * d + k]);\n                REAL pw"),
+    ("theta_index", "prod *= corr_factor(fam, diff, theta[k], p);",
+     "prod *= corr_factor(fam, diff, theta[0], p);"),
+    ("x_index_transposed",
+     "fabs((REAL)X[(size_t)i * d + k] - (REAL)X[(size_t)j * d + k]);\n                prod",
+     "fabs((REAL)X[(size_t)k * d + i % d] - (REAL)X[(size_t)j * d + k]);\n                prod"),
     ("chol_sign", "for (int m = 0; m < j; ++m) s -= rj[m] * rj[m];", "for (int m = 0; m < j; ++m) s += rj[m] * rj[m];"),
     ("chol_offdiag_index", "for (int m = 0; m < j; ++m) t -= ri[m] * rj[m];", "for (int m = 0; m < j; ++m) t -= ri[m] * rj[m + 1];"),
     ("chol_no_divide", "ri[j] = t / ljj;", "ri[j] = t;"),
@@ -27,14 +29,22 @@ MUTATIONS = [
     ("nll_missing_n", "REAL nll = logdet + (REAL)n * log(sigma2);", "REAL nll = logdet + log(sigma2);"),
     ("grad_sign", "((REAL)n / Q * alpha[i] * alpha[j] - Ri[(size_t)i * n + j]);",
      "((REAL)n / Q * alpha[i] * alpha[j] + Ri[(size_t)i * n + j]);"),
-    ("grad_missing_R", "gk += R[(size_t)i * n + j] * D *", "gk += D *"),
+    ("grad_missing_R", "gk += R[(size_t)i * n + j] * G *", "gk += G *"),
     ("back_solve_transposed", "t -= L[(size_t)m * n + i] * w[m];", "t -= L[(size_t)i * n + m] * w[m];"),
     ("pred_mse_term_dropped", "mse[j] = (double)(sigma2 * (1 - rRr + (1 - oRr) * (1 - oRr) / oRo));",
      "mse[j] = (double)(sigma2 * (1 - rRr));"),
     ("pred_mean_without_mu", "REAL m = mu, rRr = 0, oRr = 0;", "REAL m = 0, rRr = 0, oRr = 0;"),
-    ("pred_cross_power_ignored", "REAL pw = (diff == 0) ? (REAL)0 : pow(diff, p);\n                prod *= exp(-th[k] * pw);",
-     "REAL pw = diff;\n                prod *= exp(-th[k] * pw);"),
+    ("pred_cross_power_ignored", "prod *= corr_factor(fam, diff, th[k], p);",
+     "prod *= corr_factor(fam, diff, th[k], (REAL)1);"),
     ("pred_ones_forward_only", "back_solve(n, L, z, one_inv);", "memcpy(one_inv, z, sizeof(REAL) * n);"),
+    ("matern_theta_ignored", "REAL h = th * diff;", "REAL h = diff;"),
+    ("matern32_constant", "REAL c = sqrt((REAL)3);\n        return (1 + c * h)",
+     "REAL c = sqrt((REAL)2);\n        return (1 + c * h)"),
+    ("matern52_square_term_dropped", "return (1 + c * h + c * c * h * h / 3) * exp(-c * h);",
+     "return (1 + c * h) * exp(-c * h);"),
+    ("matern32_grad_factor", "return diff * c * c * h / (1 + c * h);", "return diff * c * h / (1 + c * h);"),
+    ("matern52_grad_factor", "return diff * c * c * h * (1 + c * h) / (3 * (1 + c * h + c * c * h * h / 3));",
+     "return diff * c * c * h / (3 * (1 + c * h + c * c * h * h / 3));"),
 ]
 
 

@@ -457,3 +457,120 @@ def test_prediction_extended_agrees():
     m80, v80, _ = oracle.predict(X, y, th, 1.95, delta, Xs, extended=True)
     np.testing.assert_allclose(m64, m80, rtol=1e-10, atol=1e-12)
     np.testing.assert_allclose(v64, v80, rtol=1e-7, atol=1e-14)
+
+
+# --------------------------------------------------------------------------
+# Matern families (the alternative correlation Sec. 2 names), pinned by the
+# Bessel-function definition of the Matern correlation (SciPy's K_nu), which
+# shares nothing with the oracle's closed forms
+
+MATERN = {"matern32": 1.5, "matern52": 2.5}
+
+
+def _matern_bessel(h, nu):
+    """2^(1-nu) / Gamma(nu) (sqrt(2 nu) h)^nu K_nu(sqrt(2 nu) h), 1 at h = 0."""
+    from scipy.special import gamma, kv
+    h = np.asarray(h, dtype=np.float64)
+    z = np.sqrt(2 * nu) * h
+    with np.errstate(invalid="ignore"):
+        v = 2 ** (1 - nu) / gamma(nu) * z ** nu * kv(nu, z)
+    return np.where(h == 0, 1.0, v)
+
+
+def _matern_R(X, theta, nu, delta):
+    diff = np.abs(X[:, None, :] - X[None, :, :])
+    R = np.prod(_matern_bessel(theta[None, None, :] * diff, nu), axis=2)
+    return R + delta * np.eye(X.shape[0])
+
+
+@pytest.mark.parametrize("family", sorted(MATERN))
+@pytest.mark.parametrize("extended", [False, True])
+def test_matern_entries_match_the_bessel_definition(family, extended):
+    rng = np.random.default_rng(300)
+    X = rng.random((9, 3))
+    th = np.array([0.7, 3.0, 12.0])
+    R = oracle.corr(X, th, 2.0, 1e-6, extended=extended, family=family)
+    ref = _matern_R(X, th, MATERN[family], 1e-6)
+    np.testing.assert_allclose(R, ref, rtol=1e-12, atol=1e-300)
+
+
+@pytest.mark.parametrize("family", sorted(MATERN))
+@pytest.mark.parametrize("delta", [0.0, 1e-6, 0.1])
+def test_matern_n2_closed_form(family, delta):
+    X = np.array([[0.1, 0.7], [0.45, 0.2]])
+    y = np.array([1.3, -0.4])
+    th = np.array([2.0, 0.5])
+    rho = float(np.prod(_matern_bessel(th * np.abs(X[0] - X[1]), MATERN[family])))
+    r = oracle.nll_batch(X, y, th[None], 9.9, delta, extended=True, family=family)
+    e = 1 + delta
+    assert abs(r.logdet[0] - np.log(e * e - rho * rho)) <= 1e-13
+    assert abs(r.mu[0] - 0.5 * (y[0] + y[1])) <= 1e-14
+    s2 = (y[0] - y[1]) ** 2 / (4 * (e - rho))
+    assert abs(r.sigma2[0] - s2) <= 1e-13 * s2
+
+
+@pytest.mark.parametrize("family", sorted(MATERN))
+def test_matern_likelihood_against_dense_linear_algebra(family):
+    """n = 40: log|R| = sum ln eig(R), mu and sigma2 from dense solves, all on
+    the Bessel-defined R."""
+    rng = np.random.default_rng(301)
+    n, d = 40, 3
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = np.array([1.5, 4.0, 0.8])
+    R = _matern_R(X, th, MATERN[family], 1e-6)
+    ld = np.sum(np.log(np.linalg.eigvalsh(R)))
+    one = np.ones(n)
+    mu = (one @ np.linalg.solve(R, y)) / (one @ np.linalg.solve(R, one))
+    s2 = (y - mu) @ np.linalg.solve(R, y - mu) / n
+    r = oracle.nll_batch(X, y, th[None], 2.0, 1e-6, family=family)
+    assert abs(r.logdet[0] - ld) <= 1e-9 * max(1.0, abs(ld))
+    assert abs(r.mu[0] - mu) <= 1e-9 * np.std(y)
+    assert abs(r.sigma2[0] - s2) <= 1e-9 * s2
+
+
+@pytest.mark.parametrize("family", sorted(MATERN))
+def test_matern_gradient_matches_finite_differences(family):
+    rng = np.random.default_rng(302)
+    n, d = 60, 3
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = inputs.log_uniform_theta(2, d, 0.5, 10, rng)
+    _, g = oracle.grad_batch(X, y, th, 2.0, 1e-6, family=family)
+    for t in range(2):
+        for k in range(d):
+            h = 1e-6 * th[t, k]
+            tp = th[t].copy(); tp[k] += h
+            tm = th[t].copy(); tm[k] -= h
+            fp = oracle.nll_batch(X, y, tp[None], 2.0, 1e-6, extended=True, family=family).nll[0]
+            fm = oracle.nll_batch(X, y, tm[None], 2.0, 1e-6, extended=True, family=family).nll[0]
+            fd = (fp - fm) / (2 * h)
+            assert abs(g[t, k] - fd) <= 1e-5 * max(1.0, abs(fd)), (t, k, g[t, k], fd)
+
+
+@pytest.mark.parametrize("family", sorted(MATERN))
+def test_matern_prediction_interpolates_and_limits(family):
+    """delta = 0: the predictor returns y at design points with zero mse; far
+    from the data the mean tends to mu; theta -> infinity gives R = I."""
+    rng = np.random.default_rng(303)
+    n, d = 30, 2
+    X = inputs.lhs_design(n, d, rng)
+    y = inputs.sine_response(X, rng)
+    th = np.array([3.0, 5.0])
+    mean, mse, fit = oracle.predict(X, y, th, 2.0, 0.0, X[[2, 17]], family=family)
+    np.testing.assert_allclose(mean, y[[2, 17]], rtol=0, atol=1e-9)
+    assert np.all(np.abs(mse) <= 1e-9 * fit.sigma2[0])
+    far, _, fit2 = oracle.predict(X, y, th, 2.0, 1e-6, np.array([[1e3, -1e3]]), family=family)
+    assert abs(far[0] - fit2.mu[0]) <= 1e-12
+    r = oracle.nll_batch(X, y, np.array([[1e9, 1e9]]), 2.0, 1e-6, family=family)
+    assert abs(r.logdet[0] - n * np.log1p(1e-6)) <= 1e-12
+
+
+def test_family_argument_checked():
+    X = np.random.default_rng(0).random((5, 2))
+    with pytest.raises(ValueError):
+        oracle.corr(X, np.ones(2), 2.0, 0.0, family="gauss")
+    # the power exponent is checked only for the power-exponential family
+    with pytest.raises(ValueError):
+        oracle.corr(X, np.ones(2), 2.5, 0.0)
+    oracle.corr(X, np.ones(2), 2.5, 0.0, family="matern52")
