@@ -8,6 +8,7 @@
  * correlation (eq. 2) plus a nugget delta on the diagonal:
  *
  *     R_ij   = exp(-sum_k theta_k |x_ik - x_jk|^p)   (i != j),  R_ii = 1 + delta
+ *     (or a Matern family, gp_corr below)
  *     mu     = (1' R^-1 1)^-1 1' R^-1 y                            (eq. 3)
  *     sigma2 = (y - 1 mu)' R^-1 (y - 1 mu) / n                     (eq. 3)
  *     nll    = log|R| + n ln(sigma2)                               (eq. 4)
@@ -39,7 +40,8 @@
  *   - Matrices are column-major.  Internally the order is padded to
  *     n_pad = 64 * ceil(n / 64) with an identity block, which changes neither
  *     the determinant nor the solves.
- *   - Limits: 2 <= n <= GP_NMAX, 1 <= d <= GP_DMAX, 0 < p <= 2, delta >= 0,
+ *   - Limits: 2 <= n <= GP_NMAX, 1 <= d <= GP_DMAX, 0 < p <= 2 (power
+ *     exponential family), delta >= 0,
  *     1 <= batch <= GP_BATCH_MAX (larger batches are rejected with GP_EINVAL;
  *     split them over several calls).
  */
@@ -109,8 +111,23 @@ typedef struct {
                         -1 when a mixed theta was recomputed in FP64) */
 } gp_result;
 
+/* Correlation families (gp_dataset.corr).  Each is a product over the d
+ * dimensions of one factor per dimension:
+ *   GP_CORR_POWEXP    exp(-theta_k |x_ik - x_jk|^p), 0 < p <= 2     (eq. 2)
+ *   GP_CORR_MATERN32  (1 + sqrt(3) h) exp(-sqrt(3) h)
+ *   GP_CORR_MATERN52  (1 + sqrt(5) h + 5 h^2 / 3) exp(-sqrt(5) h)
+ * with h = theta_k |x_ik - x_jk|: the Matern correlations of smoothness 3/2
+ * and 5/2, the alternative Sec. 2 names as numerically more stable; p is not
+ * used by them. */
+typedef enum {
+    GP_CORR_POWEXP = 0,
+    GP_CORR_MATERN32 = 1,
+    GP_CORR_MATERN52 = 2
+} gp_corr;
+
 /* A resident dataset.  X: device, n x d, row-major (x_i is row i).
- * y: device, n.  p, delta: host scalars of eq. 2 and the nugget. */
+ * y: device, n.  p, delta: host scalars of eq. 2 and the nugget.  corr: a
+ * gp_corr value (GP_CORR_POWEXP for eq. 2); 48 bytes. */
 typedef struct {
     const double *X;
     const double *y;
@@ -118,6 +135,8 @@ typedef struct {
     int32_t d;
     double p;
     double delta;
+    int32_t corr;
+    int32_t reserved;   /* must be 0 */
 } gp_dataset;
 
 /* Bytes of workspace that gp_nll_batch needs for `batch` thetas on a dataset
@@ -167,7 +186,8 @@ gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda,
 /* Value and adjoint gradient of nll with respect to theta for `batch`
  * thetas (FP64 only; prec must be GP_FP64):
  *   d nll/d theta_k = tr(R^-1 dR/dtheta_k) - n r'R^-1 (dR/dtheta_k) R^-1 r / (r'R^-1 r),
- *   r = y - 1 mu, dR_ij/dtheta_k = -R_ij |x_ik - x_jk|^p for i != j.
+ *   r = y - 1 mu, dR_ij/dtheta_k = -R_ij |x_ik - x_jk|^p for i != j (eq. 2;
+ *   for the Matern families the derivative of their per-dimension factor).
  * (Sec. 2: gradient-based optimisers need this next to the likelihood.)
  * R^-1 is obtained by carrying the blocked factorisation through the first
  * n_pad columns of [[R, I], [I, 0]] (order 2 n_pad), which leaves -R^-1 in
@@ -188,7 +208,7 @@ gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta,
  * its mean squared error:
  *     mean(x) = mu + r(x)' R^-1 (y - 1 mu)
  *     mse(x)  = sigma2 (1 - r' R^-1 r + (1 - 1' R^-1 r)^2 / (1' R^-1 1))
- * with r_i(x) = exp(-sum_k theta_k |x_k - x_ik|^p) (eq. 2, no nugget) and mu,
+ * with r_i(x) the correlation of x and x_i (the dataset's family, no nugget) and mu,
  * sigma2 of eq. 3.  FP64 throughout (prec must be GP_FP64).
  * Xstar: device, N x d row-major test points (may be NULL when N == 0).
  * fit: device, batch results as gp_nll_batch.  mean, mse: device, batch x N

@@ -30,7 +30,12 @@ class GPResult(ctypes.Structure):
 
 class GPDataset(ctypes.Structure):
     _fields_ = [("X", ctypes.c_void_p), ("y", ctypes.c_void_p), ("n", ctypes.c_int32),
-                ("d", ctypes.c_int32), ("p", ctypes.c_double), ("delta", ctypes.c_double)]
+                ("d", ctypes.c_int32), ("p", ctypes.c_double), ("delta", ctypes.c_double),
+                ("corr", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+# gp_corr: correlation families
+CORR = {"powexp": 0, "matern32": 1, "matern52": 2}
 
 
 class GPKernelStat(ctypes.Structure):
@@ -112,16 +117,21 @@ def pad64(n: int) -> int:
 
 
 class Dataset:
-    """A dataset resident on the GPU: X (n x d, row-major) and y, plus p, delta."""
+    """A dataset resident on the GPU: X (n x d, row-major) and y, plus p, delta
+    and the correlation family ("powexp", "matern32", "matern52")."""
 
-    def __init__(self, X, y, p: float, delta: float, device="cuda"):
+    def __init__(self, X, y, p: float, delta: float, device="cuda", corr: str = "powexp"):
+        if corr not in CORR:
+            raise ValueError(f"unknown correlation family {corr!r}")
         self.X = _dev_f64(X, device)
         self.y = _dev_f64(y, device).reshape(-1)
         self.n, self.d = self.X.shape
         self.p = float(p)
         self.delta = float(delta)
+        self.corr = corr
         self.device = self.X.device
-        self._c = GPDataset(self.X.data_ptr(), self.y.data_ptr(), self.n, self.d, self.p, self.delta)
+        self._c = GPDataset(self.X.data_ptr(), self.y.data_ptr(), self.n, self.d, self.p, self.delta,
+                            CORR[corr], 0)
 
     @property
     def c(self):

@@ -6,10 +6,11 @@
 // that consecutive lanes read consecutive points); the power terms
 // |x_ik - x_jk|^p do not depend on theta, so each lane computes them once per
 // entry and reuses them for every theta in the chunk.  The product of
-// exponentials in eq. 2 is evaluated as one exponential of the sum.
-// The kernel is bound by the HBM writes of R (8 bytes per entry per theta);
-// for p outside {1, 2} the FP64 pow() per (entry, dimension) is amortised
-// over the theta chunk.
+// exponentials in eq. 2 is evaluated as one exponential of the sum (the
+// Matern families: one exponential of the sum times the product of the
+// per-dimension polynomials).  The kernel is bound by the HBM writes of R
+// (8 bytes per entry per theta); for p outside {1, 2} the FP64 pow() per
+// (entry, dimension) is amortised over the theta chunk.
 #include <math.h>
 
 #include "kernels.hpp"
@@ -44,7 +45,7 @@ __device__ __forceinline__ void tile_of(int t, int &ti, int &tj)
     tj = t - r * (r + 1) / 2;
 }
 
-template <int DM, int PMODE>  // PMODE: 0 general p, 1 p == 1, 2 p == 2
+template <int DM, int PMODE>  // PMODE: see corr_term / corr_value
 __global__ __launch_bounds__(CB_THREADS)
 void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, double delta,
                        const double *__restrict__ theta, int batch,
@@ -94,20 +95,11 @@ void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, dou
         }
         double D[DM];
 #pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            double diff = fabs(xi[k][i] - xj[k][j]);
-            double pw;
-            if (PMODE == 2) pw = diff * diff;
-            else if (PMODE == 1) pw = diff;
-            else pw = (diff == 0.0) ? 0.0 : pow(diff, p);
-            D[k] = (k < d) ? pw : 0.0;
-        }
+        for (int k = 0; k < DM; ++k)
+            D[k] = (k < d) ? corr_term<PMODE>(fabs(xi[k][i] - xj[k][j]), p) : 0.0;
         for (int c = 0; c < nb; ++c) {
             if (mask && !mask[b0 + c]) continue;
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < DM; ++k) s = fma(th[c][k], D[k], s);
-            Rb[off + (size_t)c * bstride] = exp(-s);
+            Rb[off + (size_t)c * bstride] = corr_value<PMODE, DM>(th[c], D);
         }
     }
 }
@@ -137,15 +129,11 @@ void launch_corr_dm(const double *X, int n, int d, double p, double delta, const
 {
     const int T = np / TB;
     dim3 grid(T * (T + 1) / 2, (batch + CB_CHUNK - 1) / CB_CHUNK);
-    if (p == 2.0)
-        corr_build_kernel<DM, 2><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R,
-                                                             lda, bstride, mask);
-    else if (p == 1.0)
-        corr_build_kernel<DM, 1><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R,
-                                                             lda, bstride, mask);
-    else
-        corr_build_kernel<DM, 0><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R,
-                                                             lda, bstride, mask);
+#define GPK_CORR_LAUNCH(PM)                                                                  \
+    corr_build_kernel<DM, PM><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R, \
+                                                          lda, bstride, mask)
+    GPK_DISPATCH_PMODE(p, GPK_CORR_LAUNCH);
+#undef GPK_CORR_LAUNCH
 }
 
 }  // namespace

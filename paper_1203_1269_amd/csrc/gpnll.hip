@@ -96,7 +96,7 @@ bool dataset_ok(const gp_dataset *ds)
 {
     if (!ds || !ds->X || !ds->y) return false;
     if (ds->n < 2 || ds->n > GP_NMAX || ds->d < 1 || ds->d > GP_DMAX) return false;
-    if (!(ds->p > 0.0 && ds->p <= 2.0)) return false;
+    if (!family_ok(ds)) return false;
     if (!(ds->delta >= 0.0) || !isfinite(ds->delta)) return false;
     return true;
 }
@@ -149,8 +149,8 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
     const int np = L.np;
 
     launch_init(theta, ds->d, batch, info, stream);
-    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
-                      stream);
+    launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, A, np,
+                      L.bstride, np, stream);
     double *lk = (double *)(base + L.lk);
     factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, prec, false, nullptr,
                  (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex), lookahead);
@@ -171,8 +171,8 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
     uint8_t *mask = (uint8_t *)(base + L.mask);
     launch_fallback_mask(out, batch, mask, stream);
     launch_init(theta, ds->d, batch, info, stream, mask);
-    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, np, L.bstride, np,
-                      stream, mask);
+    launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, A, np,
+                      L.bstride, np, stream, mask);
     factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, GP_FP64, false, mask,
                  nullptr, nullptr, lookahead);
     launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
@@ -204,7 +204,7 @@ gp_status gp_corr_build(const gp_dataset *ds, int32_t batch, const double *theta
     const int np = pad64(ds->n);
     if (ldr < np) return GP_EINVAL;
     launch_init(theta, ds->d, batch, info, stream);
-    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, R, ldr,
+    launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, R, ldr,
                       (size_t)ldr * ldr, np, stream);
     return launched();
 }
@@ -290,10 +290,10 @@ gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
     int32_t *info = (int32_t *)(base + P.info);
     const int np = P.np;
     launch_init(theta, ds->d, batch, info, stream);
-    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, P.lda, P.bstride,
-                      np, stream);
-    launch_pred_rows(A, P.lda, P.bstride, np, ds->X, ds->n, ds->d, ds->p, ds->y, theta, Xstar, N,
-                     P.extra, batch, stream);
+    launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, A, P.lda,
+                      P.bstride, np, stream);
+    launch_pred_rows(A, P.lda, P.bstride, np, ds->X, ds->n, ds->d, family_p(ds), ds->y, theta,
+                     Xstar, N, P.extra, batch, stream);
     factor_batch(A, P.lda, P.bstride, np, batch, info, lpart, (double *)(base + P.lk), stream,
                  GP_FP64, false, nullptr, nullptr, nullptr, true, P.extra);
     launch_pred_reduce(A, P.lda, P.bstride, np, ds->n, lpart, np / TB, info, N, batch, fit, mean,
@@ -329,16 +329,16 @@ gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta, 
     const int lda = (int)L.lda;
 
     launch_init(theta, ds->d, batch, info, stream);
-    launch_corr_build(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, A, lda, L.bstride, np,
-                      stream);
+    launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, A, lda,
+                      L.bstride, np, stream);
     launch_border_init(A, lda, L.bstride, np, batch, stream);
     factor_batch(A, lda, L.bstride, np, batch, info, lpart, (double *)(base + L.lk), stream,
                  GP_FP64, true);
     launch_solve_reduce(A, lda, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
                         stream);
     launch_alpha(A, lda, L.bstride, np, ds->n, ds->y, out, alpha, batch, stream);
-    launch_adjoint(A, lda, L.bstride, np, ds->n, ds->d, ds->p, ds->X, theta, alpha, out, part,
-                   grad, batch, stream);
+    launch_adjoint(A, lda, L.bstride, np, ds->n, ds->d, family_p(ds), ds->X, theta, alpha, out,
+                   part, grad, batch, stream);
     return launched();
 }
 

@@ -3,8 +3,9 @@
 // With r = y - 1 mu and alpha = R^-1 r (mu at its optimum, so 1' alpha = 0
 // and the mu derivative drops out):
 //   d nll / d theta_k = tr(R^-1 dR_k) - n alpha' dR_k alpha / Q,
-//   dR_k,ij = -R_ij |x_ik - x_jk|^p (i != j),
-// i.e. g_k = sum_{i != j} R_ij D_k,ij ((n/Q) alpha_i alpha_j - (R^-1)_ij).
+//   dR_k,ij = -R_ij G_k,ij (i != j), G_k,ij = -d ln R_ij / d theta_k
+//   (|x_ik - x_jk|^p for eq. 2; corr_dlog for the Matern families),
+// i.e. g_k = sum_{i != j} R_ij G_k,ij ((n/Q) alpha_i alpha_j - (R^-1)_ij).
 // Gradient methods are what the paper names as the alternative to the
 // genetic algorithm for maximising the likelihood (Sec. 2).
 //
@@ -93,8 +94,8 @@ void alpha_kernel(const double *__restrict__ A0, int lda, size_t bstride, int np
 }
 
 // Per (lower 64 x 64 tile, theta): sum over the tile's pairs i > j of
-// w_ij D_k,ij with w_ij = R_ij ((n/Q) alpha_i alpha_j + M_ij), M = -R^-1.
-// R_ij and D_k,ij are regenerated from X; M_ij is read from the factor.
+// w_ij G_k,ij with w_ij = R_ij ((n/Q) alpha_i alpha_j + M_ij), M = -R^-1.
+// R_ij and G_k,ij are regenerated from X; M_ij is read from the factor.
 template <int DM, int PMODE>
 __global__ __launch_bounds__(GR_THREADS)
 void adjoint_tile_kernel(const double *__restrict__ A0, int lda, size_t bstride, int np, int n,
@@ -134,22 +135,14 @@ void adjoint_tile_kernel(const double *__restrict__ A0, int lda, size_t bstride,
         const int gj = J * TB + j;
         if (gi >= n || gj >= n || gi <= gj) continue;
         double D[DM];
-        double s = 0.0;
 #pragma unroll
-        for (int k = 0; k < DM; ++k) {
-            const double diff = fabs(xi[k][i] - xj[k][j]);
-            double pw;
-            if (PMODE == 2) pw = diff * diff;
-            else if (PMODE == 1) pw = diff;
-            else pw = (diff == 0.0) ? 0.0 : pow(diff, p);
-            D[k] = (k < d) ? pw : 0.0;
-            s = fma(th[k], D[k], s);
-        }
-        const double Rij = exp(-s);
+        for (int k = 0; k < DM; ++k)
+            D[k] = (k < d) ? corr_term<PMODE>(fabs(xi[k][i] - xj[k][j]), p) : 0.0;
+        const double Rij = corr_value<PMODE, DM>(th, D);
         const double Mij = A[(size_t)(np + gi) + (size_t)(np + gj) * lda];
         const double wgt = Rij * fma(nq * ai[i], aj[j], Mij);
 #pragma unroll
-        for (int k = 0; k < DM; ++k) acc[k] = fma(wgt, D[k], acc[k]);
+        for (int k = 0; k < DM; ++k) acc[k] = fma(wgt, corr_dlog<PMODE>(th[k], D[k]), acc[k]);
     }
     const int wave = tid / 64, lane = tid % 64;
 #pragma unroll
@@ -187,15 +180,11 @@ void launch_adjoint_dm(const double *A, int lda, size_t bstride, int np, int n, 
 {
     const int T = np / TB;
     dim3 grid(T * (T + 1) / 2, batch);
-    if (p == 2.0)
-        adjoint_tile_kernel<DM, 2><<<grid, GR_THREADS, 0, s>>>(A, lda, bstride, np, n, d, p, X,
-                                                                theta, alpha, res, part);
-    else if (p == 1.0)
-        adjoint_tile_kernel<DM, 1><<<grid, GR_THREADS, 0, s>>>(A, lda, bstride, np, n, d, p, X,
-                                                                theta, alpha, res, part);
-    else
-        adjoint_tile_kernel<DM, 0><<<grid, GR_THREADS, 0, s>>>(A, lda, bstride, np, n, d, p, X,
-                                                                theta, alpha, res, part);
+#define GPK_ADJ_LAUNCH(PM)                                                                  \
+    adjoint_tile_kernel<DM, PM><<<grid, GR_THREADS, 0, s>>>(A, lda, bstride, np, n, d, p, X, \
+                                                            theta, alpha, res, part)
+    GPK_DISPATCH_PMODE(p, GPK_ADJ_LAUNCH);
+#undef GPK_ADJ_LAUNCH
 }
 
 }  // namespace

@@ -21,6 +21,89 @@ constexpr int TB = 64;          // base tile / inner panel width
 
 inline int pad64(int n) { return (n + TB - 1) / TB * TB; }
 
+// Correlation families inside the library: launchers take the family where
+// they take the power exponent p.  p in (0, 2] is the power exponential of
+// eq. 2; P_MATERN32 / P_MATERN52 select the Matern families.  Kernels are
+// specialised on PMODE: 0 power exponential with general p, 1 p == 1,
+// 2 p == 2, 3 Matern 3/2, 4 Matern 5/2.
+constexpr double P_MATERN32 = -1.5;
+constexpr double P_MATERN52 = -2.5;
+
+// Family and exponent of a dataset: a known family, p in (0, 2] for the
+// power exponential, reserved field zero.
+inline bool family_ok(const gp_dataset *ds)
+{
+    if (ds->reserved != 0) return false;
+    if (ds->corr == GP_CORR_POWEXP) return ds->p > 0.0 && ds->p <= 2.0;
+    return ds->corr == GP_CORR_MATERN32 || ds->corr == GP_CORR_MATERN52;
+}
+
+inline double family_p(const gp_dataset *ds)
+{
+    return ds->corr == GP_CORR_MATERN32 ? P_MATERN32
+         : ds->corr == GP_CORR_MATERN52 ? P_MATERN52 : ds->p;
+}
+
+// Theta-independent per-dimension term: |d|^p (power exponential), |d|
+// (Matern).
+template <int PMODE>
+__device__ __forceinline__ double corr_term(double diff, double p)
+{
+    if (PMODE == 2) return diff * diff;
+    if (PMODE == 0) return (diff == 0.0) ? 0.0 : pow(diff, p);
+    return diff;
+}
+
+// Correlation from the per-dimension terms D[0..DM) (zero beyond d) and theta
+// th[0..DM).  Power exponential: exp(-sum th_k D_k).  Matern: with
+// h_k = th_k D_k and c = sqrt(3) or sqrt(5), prod_k poly(h_k) exp(-c sum h_k),
+// poly = 1 + c h (3/2) or 1 + c h + c^2 h^2 / 3 (5/2).  Where exp(-c sum h_k)
+// would underflow (c sum h_k > 700) the product is taken as
+// exp(ln(poly) - c sum h_k); with c sum h_k < 2e4 every factor is below 1.4e8,
+// so poly stays finite for d <= 32, and beyond 2e4 the value is 0 (ln(poly)
+// is then below 700).
+template <int PMODE, int DM>
+__device__ __forceinline__ double corr_value(const double *th, const double *D)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < DM; ++k) s = fma(th[k], D[k], s);
+    if (PMODE <= 2) return exp(-s);
+    constexpr double c = PMODE == 3 ? 1.7320508075688772 : 2.23606797749979;
+    const double e = c * s;
+    if (!(e < 2.0e4)) return 0.0;
+    double poly = 1.0;
+#pragma unroll
+    for (int k = 0; k < DM; ++k) {
+        const double h = th[k] * D[k];
+        poly *= (PMODE == 3) ? fma(c, h, 1.0) : fma(h, fma(c * c / 3.0, h, c), 1.0);
+    }
+    return (e <= 700.0) ? poly * exp(-e) : exp(log(poly) - e);
+}
+
+// G_k = -d ln(correlation) / d theta_k from the per-dimension term D_k:
+// D_k (power exponential); D_k c^2 h / (1 + c h) (Matern 3/2);
+// D_k c^2 h (1 + c h) / (3 (1 + c h + c^2 h^2 / 3)) (Matern 5/2).
+template <int PMODE>
+__device__ __forceinline__ double corr_dlog(double th, double D)
+{
+    if (PMODE <= 2) return D;
+    constexpr double c = PMODE == 3 ? 1.7320508075688772 : 2.23606797749979;
+    const double h = th * D;
+    if (PMODE == 3) return D * (c * c) * h / fma(c, h, 1.0);
+    return D * (c * c) * h * fma(c, h, 1.0) / (3.0 * fma(h, fma(c * c / 3.0, h, c), 1.0));
+}
+
+// Host dispatch of a kernel template on the family / exponent p.
+#define GPK_DISPATCH_PMODE(p, LAUNCH)                \
+    do {                                             \
+        if ((p) == P_MATERN32) { LAUNCH(3); }        \
+        else if ((p) == P_MATERN52) { LAUNCH(4); }   \
+        else if ((p) == 2.0) { LAUNCH(2); }          \
+        else if ((p) == 1.0) { LAUNCH(1); }          \
+        else { LAUNCH(0); }                          \
+    } while (0)
+
 // Optional per-theta mask (mask[b] == 0: the launch leaves theta b alone;
 // nullptr: all thetas) used to rerun a subset of a batch on the FP64 path.
 
@@ -66,7 +149,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
 //   row np:       1 (c < n), 0 otherwise        -> a = L^-1 1
 //   row np + 1:   y_c                            -> b = L^-1 y
 //   rows np + 2 .. np + 63: zero
-//   row np + 64 + j: r_c(x*_j) = exp(-sum_k theta_k |x*_jk - x_ck|^p) (c < n)
+//   row np + 64 + j: r_c(x*_j) = correlation of x*_j and x_c (c < n; no nugget)
 //                                                -> w_j = L^-1 r(x*_j)
 // (leading dimension np + extra, extra = 64 + 64 ceil(N / 64)).
 void launch_pred_rows(double *A, int lda, size_t bstride, int np, const double *X, int n, int d,

@@ -25,7 +25,7 @@ __device__ __forceinline__ double wave_sum(double v)
 }
 
 // one thread per (extra row, column); grid.y = theta
-template <int PMODE>   // 0 general p, 1 p == 1, 2 p == 2
+template <int PMODE, int DM>
 __global__ __launch_bounds__(256)
 void pred_rows_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
                       const double *__restrict__ X, int n, int d, double p,
@@ -49,16 +49,13 @@ void pred_rows_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
             } else if (r >= TB && r - TB < N) {
                 const double *xs = Xs + (size_t)(r - TB) * d;
                 const double *xc = X + (size_t)c * d;
-                double s = 0.0;
-                for (int k = 0; k < d; ++k) {
-                    const double diff = fabs(xs[k] - xc[k]);
-                    double pw;
-                    if (PMODE == 2) pw = diff * diff;
-                    else if (PMODE == 1) pw = diff;
-                    else pw = (diff == 0.0) ? 0.0 : pow(diff, p);
-                    s = fma(th[k], pw, s);
+                double D[DM], t[DM];
+#pragma unroll
+                for (int k = 0; k < DM; ++k) {
+                    D[k] = (k < d) ? corr_term<PMODE>(fabs(xs[k] - xc[k]), p) : 0.0;
+                    t[k] = (k < d) ? th[k] : 0.0;
                 }
-                v = exp(-s);
+                v = corr_value<PMODE, DM>(t, D);
             }
         }
         A[(size_t)r + (size_t)c * lda] = v;
@@ -185,6 +182,18 @@ void pred_point_kernel(const double *__restrict__ A0, int lda, size_t bstride, i
     }
 }
 
+template <int DM>
+void launch_pred_rows_dm(dim3 grid, double *A, int lda, size_t bstride, int np, const double *X,
+                         int n, int d, double p, const double *y, const double *theta,
+                         const double *Xs, int N, int extra, hipStream_t s)
+{
+#define GPK_PRED_LAUNCH(PM)                                                                   \
+    pred_rows_kernel<PM, DM><<<grid, 256, 0, s>>>(A, lda, bstride, np, X, n, d, p, y, theta, \
+                                                  Xs, N, extra)
+    GPK_DISPATCH_PMODE(p, GPK_PRED_LAUNCH);
+#undef GPK_PRED_LAUNCH
+}
+
 }  // namespace
 
 void launch_pred_rows(double *A, int lda, size_t bstride, int np, const double *X, int n, int d,
@@ -196,15 +205,11 @@ void launch_pred_rows(double *A, int lda, size_t bstride, int np, const double *
     const size_t total = (size_t)extra * np;
     const unsigned gx = (unsigned)min((total + 255) / 256, (size_t)4096);
     dim3 grid(gx, batch);
-    if (p == 2.0)
-        pred_rows_kernel<2><<<grid, 256, 0, s>>>(A, lda, bstride, np, X, n, d, p, y, theta, Xs, N,
-                                                 extra);
-    else if (p == 1.0)
-        pred_rows_kernel<1><<<grid, 256, 0, s>>>(A, lda, bstride, np, X, n, d, p, y, theta, Xs, N,
-                                                 extra);
+    if (d <= 8)
+        launch_pred_rows_dm<8>(grid, A, lda, bstride, np, X, n, d, p, y, theta, Xs, N, extra, s);
     else
-        pred_rows_kernel<0><<<grid, 256, 0, s>>>(A, lda, bstride, np, X, n, d, p, y, theta, Xs, N,
-                                                 extra);
+        launch_pred_rows_dm<GP_DMAX>(grid, A, lda, bstride, np, X, n, d, p, y, theta, Xs, N,
+                                     extra, s);
 }
 
 void launch_pred_reduce(const double *A, int lda, size_t bstride, int np, int n,

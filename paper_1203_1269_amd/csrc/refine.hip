@@ -177,20 +177,11 @@ void residual_kernel(const double *__restrict__ X, int n, int d, double p, doubl
             }
             double D[DM];
 #pragma unroll
-            for (int k = 0; k < DM; ++k) {
-                const double diff = fabs(xi[k][i] - xj[k][j]);
-                double pw;
-                if (PMODE == 2) pw = diff * diff;
-                else if (PMODE == 1) pw = diff;
-                else pw = (diff == 0.0) ? 0.0 : pow(diff, p);
-                D[k] = (k < d) ? pw : 0.0;
-            }
+            for (int k = 0; k < DM; ++k)
+                D[k] = (k < d) ? corr_term<PMODE>(fabs(xi[k][i] - xj[k][j]), p) : 0.0;
 #pragma unroll
             for (int c = 0; c < RF_CHUNK; ++c) {
-                double e = 0.0;
-#pragma unroll
-                for (int k = 0; k < DM; ++k) e = fma(th[c][k], D[k], e);
-                const double rij = exp(-e);
+                const double rij = corr_value<PMODE, DM>(th[c], D);
                 acc[c][0] = fma(rij, xv[c][0][j], acc[c][0]);
                 acc[c][1] = fma(rij, xv[c][1][j], acc[c][1]);
             }
@@ -306,12 +297,11 @@ void launch_residual_dm(const double *X, int n, int d, double p, double delta, c
                         hipStream_t st)
 {
     dim3 grid(np / TB, (batch + RF_CHUNK - 1) / RF_CHUNK);
-    if (p == 2.0)
-        residual_kernel<DM, 2><<<grid, RF_THREADS, 0, st>>>(X, n, d, p, delta, theta, batch, np, v, x, s);
-    else if (p == 1.0)
-        residual_kernel<DM, 1><<<grid, RF_THREADS, 0, st>>>(X, n, d, p, delta, theta, batch, np, v, x, s);
-    else
-        residual_kernel<DM, 0><<<grid, RF_THREADS, 0, st>>>(X, n, d, p, delta, theta, batch, np, v, x, s);
+#define GPK_RES_LAUNCH(PM)                                                                  \
+    residual_kernel<DM, PM><<<grid, RF_THREADS, 0, st>>>(X, n, d, p, delta, theta, batch, np, \
+                                                         v, x, s)
+    GPK_DISPATCH_PMODE(p, GPK_RES_LAUNCH);
+#undef GPK_RES_LAUNCH
 }
 
 void launch_residual(const double *X, int n, int d, double p, double delta, const double *theta,
@@ -365,12 +355,12 @@ void refine_solves(const double *A, int lda, size_t bstride, int np, const gp_da
     rhs_init_kernel<<<blocks, 256, 0, st>>>(ds->y, ds->n, np, batch, rhs);
     launch_solve2(A, lda, bstride, np, rhs, x, batch, st);
     for (int it = 0; it < sweeps; ++it) {
-        launch_residual(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, np, rhs, x, s, st);
+        launch_residual(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, np, rhs, x, s, st);
         launch_solve2(A, lda, bstride, np, s, s, batch, st);   // correction in place
         axpy_kernel<<<blocks, 256, 0, st>>>(x, s, total);
     }
     // residual of the refined solution, for the convergence flag
-    launch_residual(ds->X, ds->n, ds->d, ds->p, ds->delta, theta, batch, np, rhs, x, s, st);
+    launch_residual(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, np, rhs, x, s, st);
     refine_reduce_kernel<<<batch, RS_THREADS, 0, st>>>(x, ds->y, ds->n, np, lpart, np / TB, info, s,
                                                        sweeps, out);
 }

@@ -112,7 +112,7 @@ gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *
     for (int k = 0; k < ndatasets; ++k) {
         const gp_dataset &d = datasets[k];
         if (!d.X || !d.y || d.n < 2 || d.n > GP_NMAX || d.d < 1 || d.d > GP_DMAX ||
-            !(d.p > 0.0 && d.p <= 2.0) || !(d.delta >= 0.0) || !std::isfinite(d.delta))
+            !gpk::family_ok(&d) || !(d.delta >= 0.0) || !std::isfinite(d.delta))
             return GP_EINVAL;
     }
     gp_server *sv = new gp_server();

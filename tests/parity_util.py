@@ -16,7 +16,7 @@ def scales(y):
     return {"logdet": 1.0, "nll": 1.0, "mu": float(np.std(y)) or 1.0, "sigma2": 0.0}
 
 
-def lapack_fp64(X, y, theta, p, delta):
+def lapack_fp64(X, y, theta, p, delta, family="powexp"):
     """A second, independent FP64 evaluation of eq. (3)-(4): LAPACK's blocked
     Cholesky (SciPy) on the oracle's R, triangular solves, two-pass Q.  Used
     only to measure how far two correct FP64 orderings drift apart."""
@@ -26,7 +26,7 @@ def lapack_fp64(X, y, theta, p, delta):
         th = theta[t]
         if not np.all(np.isfinite(th)) or np.any(th < 0):
             continue
-        R = oracle.corr(X, th, p, delta)
+        R = oracle.corr(X, th, p, delta, family=family)
         try:
             L = np.tril(sla.cho_factor(R, lower=True)[0])
         except np.linalg.LinAlgError:
@@ -78,13 +78,13 @@ def to_host(res: dict) -> dict:
     return {k: v.cpu().numpy() for k, v in res.items()}
 
 
-def lapack_predict(X, y, theta, p, delta, Xs):
+def lapack_predict(X, y, theta, p, delta, Xs, family="powexp"):
     """A second, independent FP64 predictor for one theta (LAPACK Cholesky
     of the oracle's R, cho_solve, the cross-correlations from the oracle's
     correlation of the stacked points): mean and mse at the rows of Xs.  Used
     only to measure the FP64 rounding spread of the predictions."""
     n = X.shape[0]
-    R = oracle.corr(X, theta, p, delta)
+    R = oracle.corr(X, theta, p, delta, family=family)
     cf = sla.cho_factor(R, lower=True)
     one = np.ones(n)
     Ri1 = sla.cho_solve(cf, one)
@@ -94,7 +94,7 @@ def lapack_predict(X, y, theta, p, delta, Xs):
     sigma2 = res @ a / n
     # cross-correlations without the nugget: the off-diagonal block of R of
     # the stacked points [X; Xs]
-    full = oracle.corr(np.vstack([X, Xs]), theta, p, 0.0)
+    full = oracle.corr(np.vstack([X, Xs]), theta, p, 0.0, family=family)
     r = full[:n, n:]
     u = sla.cho_solve(cf, r)
     mean = mu + r.T @ a

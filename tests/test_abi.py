@@ -45,10 +45,20 @@ def test_library_exports_every_declared_symbol(lib):
         assert hasattr(lib, name)
 
 
-def test_result_struct_layout():
+def test_result_struct_layout(tmp_path):
     from paper_1203_1269_amd import binding
     assert ctypes.sizeof(binding.GPResult) == 40
-    assert ctypes.sizeof(binding.GPDataset) == 40
+    assert ctypes.sizeof(binding.GPDataset) == 48
+    assert binding.GPDataset.corr.offset == 40
+    # the header's own layout, compiled on the host
+    src = tmp_path / "sz.c"
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "gpnll.h"\n'
+                   'int main(void) { printf("%zu %zu %zu", sizeof(gp_dataset), '
+                   'offsetof(gp_dataset, corr), sizeof(gp_result)); return 0; }\n')
+    exe = tmp_path / "sz"
+    subprocess.check_call(["gcc", "-D__HIP_PLATFORM_AMD__", f"-I{ROOT}/include", "-I/opt/rocm/include",
+                           str(src), "-o", str(exe)])
+    assert subprocess.check_output([str(exe)]).decode().split() == ["48", "40", "40"]
     assert binding.header_constant("GP_NMAX") == 8192
     assert binding.header_constant("GP_DMAX") == 32
 
@@ -91,14 +101,15 @@ def test_workspace_sizing(lib):
     assert binding.predict_workspace_bytes(100, 2, bmax + 1, 10) == 0
 
 
-def _ds(X=1 << 20, y=1 << 21, n=100, d=2, p=2.0, delta=1e-6):
+def _ds(X=1 << 20, y=1 << 21, n=100, d=2, p=2.0, delta=1e-6, corr=0, reserved=0):
     from paper_1203_1269_amd import binding
-    return binding.GPDataset(X, y, n, d, p, delta)
+    return binding.GPDataset(X, y, n, d, p, delta, corr, reserved)
 
 
 @pytest.mark.parametrize("kw", [dict(n=1), dict(n=8193), dict(d=0), dict(d=33), dict(p=0.0),
                                 dict(p=2.5), dict(p=float("nan")), dict(delta=-1e-9),
-                                dict(delta=float("inf")), dict(X=0), dict(y=0)])
+                                dict(delta=float("inf")), dict(X=0), dict(y=0), dict(corr=3),
+                                dict(corr=-1), dict(reserved=1)])
 def test_invalid_dataset_rejected_on_host(lib, kw):
     from paper_1203_1269_amd import binding
     ds = _ds(**kw)
@@ -160,7 +171,6 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
 def test_bench_refuses_more_than_one_gpu():
     """bench.py measures one GPU; asked for more it exits with a message
     before touching a device."""
-    import subprocess
     import sys
     root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
     r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"],
