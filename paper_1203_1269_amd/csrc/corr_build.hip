@@ -20,7 +20,10 @@ namespace gpk {
 namespace {
 
 constexpr int CB_THREADS = 256;
-constexpr int CB_CHUNK = 32;   // thetas per workgroup
+#ifndef CB_CHUNK_N
+#define CB_CHUNK_N 128
+#endif
+constexpr int CB_CHUNK = CB_CHUNK_N;   // thetas per workgroup
 
 __global__ void init_kernel(const double *__restrict__ theta, int d, int batch,
                             int32_t *__restrict__ info, const uint8_t *__restrict__ mask)

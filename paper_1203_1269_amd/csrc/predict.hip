@@ -24,41 +24,41 @@ __device__ __forceinline__ double wave_sum(double v)
     return v;
 }
 
-// one thread per (extra row, column); grid.y = theta
+// one thread per (extra row, column), looping over the thetas: the
+// theta-independent per-dimension terms of a (test point, design point) pair
+// are computed once and reused for every theta, as in the correlation build
 template <int PMODE, int DM>
 __global__ __launch_bounds__(256)
 void pred_rows_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
                       const double *__restrict__ X, int n, int d, double p,
                       const double *__restrict__ y, const double *__restrict__ theta,
-                      const double *__restrict__ Xs, int N, int extra)
+                      const double *__restrict__ Xs, int N, int extra, int batch)
 {
-    const int b = blockIdx.y;
-    const double *th = theta + (size_t)b * d;
-    double *A = A0 + (size_t)b * bstride + np;
     const size_t total = (size_t)extra * np;
     for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
          e += (size_t)gridDim.x * blockDim.x) {
         const int r = (int)(e % extra);   // row below the matrix
         const int c = (int)(e / extra);   // column = design point
-        double v = 0.0;
-        if (c < n) {
-            if (r == 0) {
-                v = 1.0;
-            } else if (r == 1) {
-                v = y[c];
-            } else if (r >= TB && r - TB < N) {
-                const double *xs = Xs + (size_t)(r - TB) * d;
-                const double *xc = X + (size_t)c * d;
-                double D[DM], t[DM];
+        double *dst = A0 + np + (size_t)r + (size_t)c * lda;
+        if (c < n && r >= TB && r - TB < N) {
+            const double *xs = Xs + (size_t)(r - TB) * d;
+            const double *xc = X + (size_t)c * d;
+            double D[DM];
 #pragma unroll
-                for (int k = 0; k < DM; ++k) {
-                    D[k] = (k < d) ? corr_term<PMODE>(fabs(xs[k] - xc[k]), p) : 0.0;
-                    t[k] = (k < d) ? th[k] : 0.0;
-                }
-                v = corr_value<PMODE, DM>(t, D);
+            for (int k = 0; k < DM; ++k)
+                D[k] = (k < d) ? corr_term<PMODE>(fabs(xs[k] - xc[k]), p) : 0.0;
+            for (int b = 0; b < batch; ++b) {
+                double t[DM];
+#pragma unroll
+                for (int k = 0; k < DM; ++k) t[k] = (k < d) ? theta[(size_t)b * d + k] : 0.0;
+                dst[(size_t)b * bstride] = corr_value<PMODE, DM>(t, D);
             }
+        } else {
+            double v = 0.0;
+            if (c < n && r == 0) v = 1.0;
+            else if (c < n && r == 1) v = y[c];
+            for (int b = 0; b < batch; ++b) dst[(size_t)b * bstride] = v;
         }
-        A[(size_t)r + (size_t)c * lda] = v;
     }
 }
 
@@ -125,14 +125,16 @@ void pred_fit_kernel(const double *__restrict__ A0, int lda, size_t bstride, int
 }
 
 // grid (ceil(N / 64), theta); lane l of every wave <-> test point 64 x + l,
-// the 4 waves split the design points and meet in LDS
-__global__ __launch_bounds__(256)
+// the PP_WAVES waves split the design points and meet in LDS
+constexpr int PP_WAVES = 16;
+
+__global__ __launch_bounds__(64 * PP_WAVES)
 void pred_point_kernel(const double *__restrict__ A0, int lda, size_t bstride, int np, int n,
                        int N, const gp_result *__restrict__ fit, double *__restrict__ mean,
                        double *__restrict__ mse)
 {
     const int b = blockIdx.y;
-    __shared__ double part[4][3][64];
+    __shared__ double part[PP_WAVES][3][64];
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
     const int j = blockIdx.x * 64 + lane;
     const double *rows = A0 + (size_t)b * bstride + np;
@@ -141,7 +143,7 @@ void pred_point_kernel(const double *__restrict__ A0, int lda, size_t bstride, i
     double s1 = 0.0, s2 = 0.0, s3 = 0.0;
     if (j < N) {
         const double *wj = rows + TB + j;
-        for (int i = wave; i < n; i += 4) {
+        for (int i = wave; i < n; i += PP_WAVES) {
             const double a = rows[(size_t)i * lda], bb = rows[(size_t)i * lda + 1];
             const double w = wj[(size_t)i * lda];
             s1 = fma(w, fma(-mu, a, bb), s1);
@@ -154,19 +156,20 @@ void pred_point_kernel(const double *__restrict__ A0, int lda, size_t bstride, i
     part[wave][2][lane] = s3;
     // a.a = 1' R^-1 1, shared by all test points of this theta
     double aa = 0.0;
-    for (int i = threadIdx.x; i < n; i += 256) {
+    for (int i = threadIdx.x; i < n; i += 64 * PP_WAVES) {
         const double a = rows[(size_t)i * lda];
         aa = fma(a, a, aa);
     }
     aa = wave_sum(aa);
-    __shared__ double aaw[4];
+    __shared__ double aaw[PP_WAVES];
     if (lane == 0) aaw[wave] = aa;
     __syncthreads();
     if (wave == 0 && j < N) {
-        aa = aaw[0] + aaw[1] + aaw[2] + aaw[3];
+        aa = 0.0;
+        for (int w = 0; w < PP_WAVES; ++w) aa += aaw[w];
         s1 = s2 = s3 = 0.0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < PP_WAVES; ++w) {
             s1 += part[w][0][lane];
             s2 += part[w][1][lane];
             s3 += part[w][2][lane];
@@ -183,13 +186,14 @@ void pred_point_kernel(const double *__restrict__ A0, int lda, size_t bstride, i
 }
 
 template <int DM>
-void launch_pred_rows_dm(dim3 grid, double *A, int lda, size_t bstride, int np, const double *X,
-                         int n, int d, double p, const double *y, const double *theta,
-                         const double *Xs, int N, int extra, hipStream_t s)
+void launch_pred_rows_dm(unsigned grid, double *A, int lda, size_t bstride, int np,
+                         const double *X, int n, int d, double p, const double *y,
+                         const double *theta, const double *Xs, int N, int extra, int batch,
+                         hipStream_t s)
 {
 #define GPK_PRED_LAUNCH(PM)                                                                   \
     pred_rows_kernel<PM, DM><<<grid, 256, 0, s>>>(A, lda, bstride, np, X, n, d, p, y, theta, \
-                                                  Xs, N, extra)
+                                                  Xs, N, extra, batch)
     GPK_DISPATCH_PMODE(p, GPK_PRED_LAUNCH);
 #undef GPK_PRED_LAUNCH
 }
@@ -203,13 +207,13 @@ void launch_pred_rows(double *A, int lda, size_t bstride, int np, const double *
     ProfScope ps(K_PRED_ROWS, 3.0 * d * (double)N * n * batch, 8.0 * extra * (double)np * batch,
                  s);
     const size_t total = (size_t)extra * np;
-    const unsigned gx = (unsigned)min((total + 255) / 256, (size_t)4096);
-    dim3 grid(gx, batch);
+    const unsigned grid = (unsigned)min((total + 255) / 256, (size_t)16384);
     if (d <= 8)
-        launch_pred_rows_dm<8>(grid, A, lda, bstride, np, X, n, d, p, y, theta, Xs, N, extra, s);
+        launch_pred_rows_dm<8>(grid, A, lda, bstride, np, X, n, d, p, y, theta, Xs, N, extra,
+                               batch, s);
     else
         launch_pred_rows_dm<GP_DMAX>(grid, A, lda, bstride, np, X, n, d, p, y, theta, Xs, N,
-                                     extra, s);
+                                     extra, batch, s);
 }
 
 void launch_pred_reduce(const double *A, int lda, size_t bstride, int np, int n,
@@ -221,7 +225,8 @@ void launch_pred_reduce(const double *A, int lda, size_t bstride, int np, int n,
     pred_fit_kernel<<<batch, 256, 0, s>>>(A, lda, bstride, np, n, lpart, nparts, info, fit);
     if (N > 0) {
         dim3 grid((N + 63) / 64, batch);
-        pred_point_kernel<<<grid, 256, 0, s>>>(A, lda, bstride, np, n, N, fit, mean, mse);
+        pred_point_kernel<<<grid, 64 * PP_WAVES, 0, s>>>(A, lda, bstride, np, n, N, fit, mean,
+                                                         mse);
     }
 }
 
