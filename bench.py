@@ -131,6 +131,44 @@ def syrk_traffic():
     return SYRK_TRAFFIC["bytes_per_launch"]
 
 
+def multi_leg(args, dev, per=16):
+    """The 64 serving datasets (uneven n and d), `per` thetas each, in one
+    gp_nll_multi call per step; beside it the same work as one gp_nll_batch
+    call per dataset on one stream."""
+    import numpy as np
+    import torch
+    from paper_1203_1269_amd import binding, inputs
+    sets = inputs.serving_datasets()
+    ds = [binding.Dataset(s.X, s.y, s.p, s.delta, device=dev) for s in sets]
+    rng = np.random.default_rng(9)
+    th = [torch.as_tensor(inputs.log_uniform_theta(per, d.d, 0.05, 20.0, rng),
+                          dtype=torch.float64, device=dev) for d in ds]
+    ws = None
+    binding.nll_multi(ds, th)
+    torch.cuda.synchronize()
+    steps = max(1, args.steps // 2)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = binding.nll_multi(ds, th)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    ok = int(sum(int((r["info"] == 0).sum()) for r in res))
+    wsb = max(binding.workspace_bytes(d.n, d.d, per) for d in ds)
+    ws = binding.alloc_workspace(wsb, dev)
+    t1 = time.perf_counter()
+    for _ in range(steps):
+        for d, t in zip(ds, th):
+            binding.nll_batch(d, t, ws=ws)
+    torch.cuda.synchronize()
+    ds_ = (time.perf_counter() - t1) / steps
+    del ws
+    torch.cuda.empty_cache()
+    total = per * len(ds)
+    return {"datasets": len(ds), "thetas_per_dataset": per, "evaluations": total,
+            "results_ok": ok, "ms_per_call": dt * 1e3, "evals_per_s": total / dt,
+            "sequential_batches_ms": ds_ * 1e3, "sequential_evals_per_s": total / ds_}
+
+
 def serving_leg(args, dev):
     """64 resident datasets (n uniform over multiples of 64 in [256, 6144],
     d in 2..12, p in {1.5, 1.95, 2}); a closed-loop burst measures the
@@ -453,6 +491,7 @@ def main():
     if not args.no_ga:
         line["ga_fit"] = ga_leg(args, dev)
     if not args.no_serving:
+        line["multi_dataset"] = multi_leg(args, dev)
         line["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))

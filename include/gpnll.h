@@ -220,6 +220,27 @@ gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
                      const double *Xstar, int32_t N, int32_t prec, void *ws, size_t ws_bytes,
                      gp_result *fit, double *mean, double *mse, hipStream_t stream);
 
+/* Uneven-n batching in one call: counts[k] thetas for dataset ds[k]
+ * (k < nds; any n, d and correlation family per dataset), the thetas of
+ * dataset k stored as a counts[k] x d_k row-major block, blocks concatenated
+ * in dataset order in `theta` (device); results in the same order in `out`
+ * (device, sum of counts).  Each dataset's thetas run as one gp_nll_batch
+ * (without the factorisation lookahead), and the per-dataset batches run
+ * side by side on a pool of four library-owned streams (default priority,
+ * created on first use per device and caller stream and kept for the life
+ * of the process) that fork from and join back into `stream`; the paper
+ * evaluated one theta at a time (Sec. 3).  Each result is bitwise the one
+ * gp_nll_batch gives for that dataset and theta.  ds, counts: host arrays;
+ * counts[k] = 0 skips dataset k (its descriptor is then not read).  ws: at
+ * least gp_multi_workspace_bytes(ds, nds, counts, prec) bytes, 256-byte
+ * aligned (one gp_nll_batch workspace per dataset with work).  Returns
+ * GP_EINVAL for an invalid descriptor or count before anything is launched. */
+size_t gp_multi_workspace_bytes(const gp_dataset *ds, int32_t nds, const int32_t *counts,
+                                int32_t prec);
+gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
+                       const double *theta, int32_t prec, void *ws, size_t ws_bytes,
+                       gp_result *out, hipStream_t stream);
+
 /* ------------------------------------------------------------------------ */
 /* Continuous-batching request server (host API over gp_nll_batch).
  * The paper evaluates one theta at a time and notes that evaluating the

@@ -84,6 +84,10 @@ def lib():
         L.gp_grad_workspace_bytes.restype = sz
         L.gp_nll_grad.argtypes = [ctypes.POINTER(GPDataset), i32, vp, i32, vp, sz, vp, vp, vp]
         L.gp_nll_grad.restype = ctypes.c_int
+        L.gp_multi_workspace_bytes.argtypes = [ctypes.POINTER(GPDataset), i32, vp, i32]
+        L.gp_multi_workspace_bytes.restype = sz
+        L.gp_nll_multi.argtypes = [ctypes.POINTER(GPDataset), i32, vp, vp, i32, vp, sz, vp, vp]
+        L.gp_nll_multi.restype = ctypes.c_int
         L.gp_predict_workspace_bytes.argtypes = [i32, i32, i32, i32]
         L.gp_predict_workspace_bytes.restype = sz
         L.gp_predict.argtypes = [ctypes.POINTER(GPDataset), i32, vp, vp, i32, i32, vp, sz, vp, vp,
@@ -241,6 +245,38 @@ def profile_end() -> dict:
 
 def grad_workspace_bytes(n: int, d: int, batch: int) -> int:
     return int(lib().gp_grad_workspace_bytes(n, d, batch))
+
+
+def nll_multi(datasets, thetas, prec: str = "fp64", ws: torch.Tensor | None = None):
+    """Uneven-n batching in one call (gp_nll_multi): thetas[k] (B_k x d_k)
+    for datasets[k].  Returns a list of result dicts (device tensors), one
+    per dataset, as nll_batch."""
+    nds = len(datasets)
+    assert nds == len(thetas) and nds > 0
+    dev = datasets[0].device
+    blocks = [_dev_f64(t, dev).reshape(-1, ds.d) for ds, t in zip(datasets, thetas)]
+    counts = (ctypes.c_int32 * nds)(*[b.shape[0] for b in blocks])
+    arr = (GPDataset * nds)(*[ds._c for ds in datasets])
+    th = torch.cat([b.reshape(-1) for b in blocks]) if blocks else torch.empty(0)
+    th = th.contiguous()
+    need = int(lib().gp_multi_workspace_bytes(arr, nds, ctypes.cast(counts, ctypes.c_void_p),
+                                              PRECISIONS[prec]))
+    if need == 0:
+        raise GPError("gp_multi_workspace_bytes rejected the sizes")
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, dev)
+    total = sum(counts)
+    out = torch.empty((max(total, 1), 5), dtype=torch.float64, device=dev)
+    st = lib().gp_nll_multi(arr, nds, ctypes.cast(counts, ctypes.c_void_p),
+                            ctypes.c_void_p(th.data_ptr()), PRECISIONS[prec],
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                            ctypes.c_void_p(out.data_ptr()), _stream_ptr())
+    _check(st, "gp_nll_multi")
+    res, o = [], 0
+    for c in counts:
+        res.append(unpack_results(out[o:o + c]))
+        o += c
+    return res
 
 
 def predict_workspace_bytes(n: int, d: int, batch: int, N: int) -> int:

@@ -130,6 +130,8 @@ size_t gp_workspace_bytes(int32_t n, int32_t d, int32_t batch, int32_t prec)
 
 namespace gpk {
 
+bool dataset_valid(const gp_dataset *ds) { return dataset_ok(ds); }
+
 gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
                          void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream,
                          bool lookahead)

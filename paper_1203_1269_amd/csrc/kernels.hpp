@@ -161,6 +161,9 @@ void launch_pred_reduce(const double *A, int lda, size_t bstride, int np, int n,
                         const double *lpart, int nparts, const int32_t *info, int N, int batch,
                         gp_result *fit, double *mean, double *mse, hipStream_t s);
 
+// Host-side check of a dataset descriptor (pointers, sizes, family, delta).
+bool dataset_valid(const gp_dataset *ds);
+
 // gp_nll_batch with the lookahead of the factorisation switchable (the
 // request server runs several calls side by side and turns it off).
 gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
@@ -170,7 +173,7 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
 // GP_MIXED trailing update: digits of the panel rows pe .. np-1 (OZ_S slices)
 // and one exponent per row, then the INT8-MFMA product over the columns
 // [cs, ce) (multiples of 64 from pe).  ozaki_handles() tells whether the
-// shape is the rank-256 one these kernels take.
+// shape is the rank-OZ_RANK one these kernels take.
 #ifndef OZ_S
 #define OZ_S GP_MIXED_DIGITS
 #endif

@@ -160,6 +160,29 @@ def test_invalid_call_arguments_rejected_on_host(lib):
     assert pred(a1=0) == binding.GP_EINVAL
 
 
+def test_multi_dataset_call_checked_on_host(lib):
+    from paper_1203_1269_amd import binding
+    vp = ctypes.c_void_p
+    arr = (binding.GPDataset * 3)(_ds(n=100, d=2), _ds(n=700, d=5), _ds(n=2, d=2, p=0.0))
+    counts = (ctypes.c_int32 * 3)(4, 7, 0)
+    need = lib.gp_multi_workspace_bytes(arr, 3, counts, 0)
+    a = lib.gp_workspace_bytes(100, 2, 4, 0)
+    b = lib.gp_workspace_bytes(700, 5, 7, 0)
+    up = lambda x: (x + 255) // 256 * 256
+    assert need == up(a) + up(b)     # dataset 2 has no work: its descriptor is not read
+    assert lib.gp_multi_workspace_bytes(arr, 3, (ctypes.c_int32 * 3)(4, -1, 0), 0) == 0
+    assert lib.gp_multi_workspace_bytes(arr, 3, counts, 9) == 0
+    assert lib.gp_multi_workspace_bytes(arr, 3, (ctypes.c_int32 * 3)(0, 0, 0), 0) == 256
+    call = lambda arr_, n_, c_, ws_, wsb: lib.gp_nll_multi(arr_, n_, c_, vp(1 << 22), 0, ws_, wsb,
+                                                           vp(1 << 24), None)
+    assert call(arr, 0, counts, vp(1 << 23), need) == binding.GP_EINVAL
+    assert call(arr, 3, counts, vp((1 << 23) + 8), need) == binding.GP_EINVAL
+    assert call(arr, 3, counts, vp(1 << 23), need - 1) == binding.GP_EWORKSPACE
+    assert call(arr, 3, (ctypes.c_int32 * 3)(4, 7, 1), vp(1 << 23), 1 << 40) == binding.GP_EINVAL
+    assert call(arr, 3, (ctypes.c_int32 * 3)(4, 65536, 0), vp(1 << 23), 1 << 40) == binding.GP_EINVAL
+    assert call(arr, 3, (ctypes.c_int32 * 3)(0, 0, 0), vp(1 << 23), 256) == binding.GP_OK
+
+
 def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     from paper_1203_1269_amd import binding
     monkeypatch.setattr(binding, "LIB_PATH", str(tmp_path / "missing.so"))
