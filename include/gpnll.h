@@ -226,7 +226,7 @@ gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
  * in dataset order in `theta` (device); results in the same order in `out`
  * (device, sum of counts).  Each dataset's thetas run as one gp_nll_batch
  * (without the factorisation lookahead), and the per-dataset batches run
- * side by side on a pool of four library-owned streams (default priority,
+ * side by side on a pool of eight library-owned streams (default priority,
  * created on first use per device and caller stream and kept for the life
  * of the process) that fork from and join back into `stream`; the paper
  * evaluated one theta at a time (Sec. 3).  Each result is bitwise the one
