@@ -109,3 +109,47 @@ def pred_tolerance(m64, v64, m80, v80, mlap, vlap, sd_y, sigma2, floor=FP64_TOL)
     em = np.fmax(np.abs(m64 - m80), np.abs(mlap - m80)) / np.maximum(np.abs(m80), sd_y)
     ev = np.fmax(np.abs(v64 - v80), np.abs(vlap - v80)) / np.maximum(np.abs(v80), sigma2)
     return np.maximum(floor, SLACK * em), np.maximum(floor, SLACK * ev)
+
+
+def _dlog_corr(diff, th, p, family):
+    """-d ln(correlation factor) / d theta_k for one dimension (test-side
+    restatement used only for the LAPACK gradient below)."""
+    if family == "powexp":
+        return np.where(diff == 0, 0.0, np.abs(diff) ** p)
+    h = th * diff
+    if family == "matern32":
+        c = np.sqrt(3.0)
+        return diff * c * c * h / (1 + c * h)
+    c = np.sqrt(5.0)
+    return diff * c * c * h * (1 + c * h) / (3 * (1 + c * h + c * c * h * h / 3))
+
+
+def lapack_grad(X, y, theta, p, delta, family="powexp"):
+    """A second, independent FP64 gradient of nll (adjoint formula with R^-1
+    from LAPACK's Cholesky and dense NumPy sums), to measure the FP64
+    rounding spread of the gradient.  theta: B x d."""
+    n, d = X.shape
+    out = np.full(theta.shape, np.nan)
+    one = np.ones(n)
+    for t in range(theta.shape[0]):
+        R = oracle.corr(X, theta[t], p, delta, family=family)
+        cf = sla.cho_factor(R, lower=True)
+        Ri = sla.cho_solve(cf, np.eye(n))
+        mu = (one @ sla.cho_solve(cf, y)) / (one @ sla.cho_solve(cf, one))
+        alpha = sla.cho_solve(cf, y - mu)
+        Q = (y - mu) @ alpha
+        Wm = (n / Q) * np.outer(alpha, alpha) - Ri
+        Roff = R - np.diag(np.diag(R))
+        for k in range(d):
+            diff = np.abs(X[:, k, None] - X[None, :, k])
+            out[t, k] = np.sum(Roff * _dlog_corr(diff, theta[t, k], p, family) * Wm)
+    return out
+
+
+def grad_tolerance(g64, g80, glap, floor=1e-9, slack=20.0):
+    """Per-component bar for a gradient: max(floor, slack x the larger
+    distance of two FP64 codes from the 80-bit oracle), relative to
+    max(|g80|, 1)."""
+    scale = np.maximum(np.abs(g80), 1.0)
+    spread = np.fmax(np.abs(g64 - g80), np.abs(glap - g80)) / scale
+    return np.maximum(floor, slack * spread), scale
