@@ -197,6 +197,21 @@ def serving_leg(args, dev):
         summ["failed"] = int(sum(1 for r in res if r["info"] != 0))
         out[f"poisson_{frac}"] = summ
     srv.close()
+    # the same burst and the 0.5x stream with every micro-batch launched as a
+    # captured graph
+    srv = serving.Server(ds, arena_bytes=arena, max_batch=16, nstreams=8, graphs=True)
+    lat, _, bsz, wall = serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
+                                       [r[1] for r in burst])
+    g = {"saturation_evals_per_s": len(burst) / wall}
+    reqs = inputs.serving_requests(sets, count=N, rate=0.5 * sat, seed=8)
+    lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                         [r[1] for r in reqs])
+    summ = serving.latency_summary(lat, wall)
+    summ["offered_rate"] = 0.5 * sat
+    summ["failed"] = int(sum(1 for r in res if r["info"] != 0))
+    g["poisson_0.5"] = summ
+    out["graphs"] = g
+    srv.close()
     return out
 
 

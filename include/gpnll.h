@@ -283,7 +283,10 @@ typedef struct {
     int32_t max_batch;
     int32_t nstreams;
     int32_t prec;
-    int32_t pad_;
+    int32_t graphs;          /* 1: launch each micro-batch as a captured HIP
+                                graph (kept per stream and updated in place
+                                for the same dataset and batch size); 0: direct
+                                kernel launches */
 } gp_server_config;
 
 gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *arena,

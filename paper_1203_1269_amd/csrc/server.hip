@@ -15,6 +15,14 @@
 // rest of its batch and of the other streams, so a request's result is
 // bitwise the one it gets alone.  Admission is strictly in arrival order of
 // the oldest request (no overtaking), so no request starves.
+//
+// With graphs on, each micro-batch's kernel sequence is captured into a HIP
+// graph and launched as one: the executable graph of a stream is kept and,
+// when the next micro-batch on that stream has the same dataset and batch
+// size (same launch sequence, new buffers), updated in place instead of
+// instantiated again.  A stream's graph is only updated after its previous
+// micro-batch retired.  No memset nodes are captured (every kernel writes
+// what it needs).  Graphs are not used while per-launch profiling is on.
 #include <math.h>
 #include <string.h>
 
@@ -33,6 +41,7 @@ struct gp_server {
     Arena arena;
     int max_batch = 32;
     int prec = GP_FP64;
+    bool graphs = false;
     std::deque<gp_request> pending;
     struct Stream {
         hipStream_t s = nullptr;
@@ -41,6 +50,8 @@ struct gp_server {
         gp_result *h_out = nullptr;     // pinned results, max_batch
         bool busy = false;
         int dataset = -1, B = 0;
+        hipGraphExec_t exec = nullptr;   // kept executable graph (graphs on)
+        int g_dataset = -1, g_B = 0;     // the launch sequence it holds
         size_t off = 0, bytes = 0;
         std::vector<int64_t> ids;
     };
@@ -60,6 +71,50 @@ size_t batch_bytes(const gp_dataset &d, int B, int prec, size_t &ws_bytes, size_
     return out_off + Arena::round(sizeof(gp_result) * (size_t)B);
 }
 
+// One micro-batch's gp_nll_batch sequence as a graph on st.s.  Falls back to
+// launching the kernels directly when capture or instantiation fails.
+gp_status launch_captured(gp_server::Stream &st, int k, const gp_dataset &d, int B,
+                          const double *d_theta, int prec, void *ws, size_t ws_bytes,
+                          gp_result *d_out)
+{
+    hipGraph_t g = nullptr;
+    if (hipStreamBeginCapture(st.s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+        (void)hipGetLastError();
+        return nll_batch_impl(&d, B, d_theta, prec, ws, ws_bytes, d_out, st.s, false);
+    }
+    const gp_status rc = nll_batch_impl(&d, B, d_theta, prec, ws, ws_bytes, d_out, st.s, false);
+    const hipError_t e = hipStreamEndCapture(st.s, &g);
+    if (e != hipSuccess || rc != GP_OK || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();
+        return nll_batch_impl(&d, B, d_theta, prec, ws, ws_bytes, d_out, st.s, false);
+    }
+    bool ok = false;
+    if (st.exec && st.g_dataset == k && st.g_B == B) {
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        ok = hipGraphExecUpdate(st.exec, g, &bad, &res) == hipSuccess &&
+             res == hipGraphExecUpdateSuccess;
+        (void)hipGetLastError();
+    }
+    if (!ok) {
+        if (st.exec) (void)hipGraphExecDestroy(st.exec);
+        st.exec = nullptr;
+        st.g_dataset = -1;
+        ok = hipGraphInstantiate(&st.exec, g, nullptr, nullptr, 0) == hipSuccess;
+        if (ok) {
+            st.g_dataset = k;
+            st.g_B = B;
+        } else {
+            st.exec = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    (void)hipGraphDestroy(g);
+    if (!ok) return nll_batch_impl(&d, B, d_theta, prec, ws, ws_bytes, d_out, st.s, false);
+    return hipGraphLaunch(st.exec, st.s) == hipSuccess ? GP_OK : GP_ELAUNCH;
+}
+
 bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_request> &reqs)
 {
     const gp_dataset &d = sv->ds[k];
@@ -76,7 +131,10 @@ bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_re
     (void)hipMemcpyAsync(d_theta, st.h_theta, sizeof(double) * (size_t)B * d.d,
                          hipMemcpyHostToDevice, st.s);
     // micro-batches already run side by side: no lookahead stream per call
-    gp_status rc = nll_batch_impl(&d, B, d_theta, sv->prec, base, ws_bytes, d_out, st.s, false);
+    const gp_status rc =
+        (sv->graphs && !prof_enabled())
+            ? launch_captured(st, k, d, B, d_theta, sv->prec, base, ws_bytes, d_out)
+            : nll_batch_impl(&d, B, d_theta, sv->prec, base, ws_bytes, d_out, st.s, false);
     (void)hipMemcpyAsync(st.h_out, d_out, sizeof(gp_result) * B, hipMemcpyDeviceToHost, st.s);
     (void)hipEventRecord(st.done, st.s);
     st.busy = true;
@@ -108,6 +166,7 @@ gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *
         return GP_EINVAL;
     if (cfg->prec != GP_FP64 && cfg->prec != GP_MIXED && cfg->prec != GP_MIXED_FAST)
         return GP_EINVAL;
+    if (cfg->graphs != 0 && cfg->graphs != 1) return GP_EINVAL;
     if (((uintptr_t)arena & 255) != 0) return GP_EINVAL;
     for (int k = 0; k < ndatasets; ++k) {
         const gp_dataset &d = datasets[k];
@@ -121,6 +180,7 @@ gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *
     sv->arena.reset(arena_bytes);
     sv->max_batch = cfg->max_batch;
     sv->prec = cfg->prec;
+    sv->graphs = cfg->graphs == 1;
     sv->streams.resize(cfg->nstreams);
     for (auto &st : sv->streams) {
         bool ok = hipStreamCreateWithFlags(&st.s, hipStreamNonBlocking) == hipSuccess &&
@@ -212,6 +272,7 @@ gp_status gp_server_destroy(gp_server *sv)
     if (!sv) return GP_EINVAL;
     for (auto &st : sv->streams) {
         if (st.s) (void)hipStreamSynchronize(st.s);
+        if (st.exec) (void)hipGraphExecDestroy(st.exec);
         if (st.done) (void)hipEventDestroy(st.done);
         if (st.s) (void)hipStreamDestroy(st.s);
         if (st.h_theta) (void)hipHostFree(st.h_theta);

@@ -83,3 +83,28 @@ def test_server_mixed_matches_alone(env):
         for key in ("logdet", "mu", "sigma2", "nll"):
             assert res[q][key] == a[key], (q, key)
         assert res[q]["info"] == a["info"] == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_server_graphs_match_direct_launches(env, prec):
+    """Micro-batches launched as captured graphs (kept per stream, updated in
+    place when dataset and batch size repeat, instantiated anew otherwise):
+    every result bitwise the same as with direct launches, with eager calls
+    of the library between the server runs."""
+    binding, serving, sets, ds = env
+    reqs = inputs.serving_requests(sets, count=240, rate=1e6, seed=43)
+    runs = []
+    for graphs in (False, True, True):
+        srv = serving.Server(ds, arena_bytes=2 << 30, max_batch=8, nstreams=6, prec=prec,
+                             graphs=graphs)
+        lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                             [r[1] for r in reqs], time_limit=120)
+        assert srv.outstanding() == 0 and srv.arena_used() == 0
+        srv.close()
+        assert all(r is not None for r in res)
+        runs.append(res)
+        alone(binding, ds, reqs[0][1], reqs[0][2])   # eager work between the runs
+    for q in range(len(reqs)):
+        for key in ("logdet", "mu", "sigma2", "nll", "info"):
+            assert runs[1][q][key] == runs[0][q][key], (q, key)
+            assert runs[2][q][key] == runs[0][q][key], (q, key)
