@@ -131,6 +131,28 @@ def syrk_traffic():
     return SYRK_TRAFFIC["bytes_per_launch"]
 
 
+def conditioning(w, dev, chunk=32):
+    """kappa_hat = (max_j L_jj / min_j L_jj)^2 of every theta of the workload
+    (R from gp_corr_build, L from gp_cholesky_batch), in chunks of thetas."""
+    import numpy as np
+    import torch
+    from paper_1203_1269_amd import binding
+    ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
+    kap = []
+    for c0 in range(0, w.B, chunk):
+        R, info = binding.corr_build(ds, w.theta[c0:c0 + chunk])
+        info2, _ = binding.cholesky_batch(R, w.n)
+        dg = torch.diagonal(R, dim1=1, dim2=2)[:, :w.n]
+        k = (dg.max(dim=1).values / dg.min(dim=1).values) ** 2
+        k[(info != 0) | (info2 != 0)] = float("nan")
+        kap.append(k.cpu().numpy())
+        del R
+    torch.cuda.empty_cache()
+    kap = np.concatenate(kap)
+    return {"kappa_hat_median": float(np.nanmedian(kap)), "kappa_hat_max": float(np.nanmax(kap)),
+            "kappa_hat_over_1e8": int(np.sum(kap > 1e8))}
+
+
 def multi_leg(args, dev, per=16):
     """The 64 serving datasets (uneven n and d), `per` thetas each, in one
     gp_nll_multi call per step; beside it the same work as one gp_nll_batch
@@ -497,6 +519,7 @@ def main():
     line.update(mixed)
     del ws
     torch.cuda.empty_cache()
+    line["conditioning"] = conditioning(w, dev)
     if not args.no_large:
         line["large_n8192"] = large_leg(args, dev)
     if not args.no_grad:

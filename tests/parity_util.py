@@ -71,6 +71,9 @@ def compare(gpu: dict, r80, tol: dict, y, label=""):
         assert bad.size == 0, (f"{label}: {k} off for thetas {np.nonzero(ok)[0][bad]}: "
                                f"err {e[bad]} tol {tol[k][ok][bad]}")
         worst[k] = float(e.max()) if e.size else 0.0
+    # how many thetas needed a bar above the floor (ill-conditioned R)
+    relaxed = {k: int(np.sum(tol[k][ok] > np.min(tol[k]))) for k in tol}
+    print(f"{label}: thetas with a bar above the floor per output: {relaxed}", flush=True)
     return worst
 
 
