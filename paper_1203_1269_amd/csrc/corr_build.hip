@@ -23,7 +23,7 @@ constexpr int CB_THREADS = 256;
 #ifndef CB_CHUNK_N
 #define CB_CHUNK_N 128
 #endif
-constexpr int CB_CHUNK = CB_CHUNK_N;   // thetas per workgroup
+constexpr int CB_CHUNK = CB_CHUNK_N;   // most thetas per workgroup
 
 __global__ void init_kernel(const double *__restrict__ theta, int d, int batch,
                             int32_t *__restrict__ info, const uint8_t *__restrict__ mask)
@@ -51,7 +51,7 @@ __device__ __forceinline__ void tile_of(int t, int &ti, int &tj)
 template <int DM, int PMODE>  // PMODE: see corr_term / corr_value
 __global__ __launch_bounds__(CB_THREADS)
 void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, double delta,
-                       const double *__restrict__ theta, int batch,
+                       const double *__restrict__ theta, int batch, int chunk,
                        double *__restrict__ R, int lda, size_t bstride,
                        const uint8_t *__restrict__ mask)
 {
@@ -62,8 +62,8 @@ void corr_build_kernel(const double *__restrict__ X, int n, int d, double p, dou
     int ti, tj;
     tile_of(blockIdx.x, ti, tj);
     const int tid = threadIdx.x;
-    const int b0 = blockIdx.y * CB_CHUNK;
-    const int nb = min(CB_CHUNK, batch - b0);
+    const int b0 = blockIdx.y * chunk;
+    const int nb = min(chunk, batch - b0);   // chunk <= CB_CHUNK
     if (mask) {   // a chunk with no selected theta has nothing to write
         int any = 0;
         for (int c = 0; c < nb; ++c) any |= mask[b0 + c];
@@ -131,10 +131,15 @@ void launch_corr_dm(const double *X, int n, int d, double p, double delta, const
                     const uint8_t *mask)
 {
     const int T = np / TB;
-    dim3 grid(T * (T + 1) / 2, (batch + CB_CHUNK - 1) / CB_CHUNK);
+    // thetas per workgroup: CB_CHUNK where there are tiles enough to fill the
+    // GPU, fewer for small matrices (more workgroups, power terms recomputed)
+    const long tiles = (long)T * (T + 1) / 2;
+    int chunk = CB_CHUNK;
+    while (chunk > 8 && tiles * ((batch + chunk - 1) / chunk) < 1024) chunk /= 2;
+    dim3 grid((unsigned)tiles, (batch + chunk - 1) / chunk);
 #define GPK_CORR_LAUNCH(PM)                                                                  \
-    corr_build_kernel<DM, PM><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch, R, \
-                                                          lda, bstride, mask)
+    corr_build_kernel<DM, PM><<<grid, CB_THREADS, 0, s>>>(X, n, d, p, delta, theta, batch,    \
+                                                          chunk, R, lda, bstride, mask)
     GPK_DISPATCH_PMODE(p, GPK_CORR_LAUNCH);
 #undef GPK_CORR_LAUNCH
 }
