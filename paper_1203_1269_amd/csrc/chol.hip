@@ -440,12 +440,15 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
 
 namespace {
 
-// Side stream (and fork/join events) for the lookahead of one caller stream,
-// created on first use per (device, caller stream) and kept for the life of
-// the process.  Default priority, non-blocking.
+// Side streams (and their events) of one caller stream, created on first use
+// per (device, caller stream) and kept for the life of the process: `s` for
+// the lookahead trailing updates, `solve` for the solve segments.  Default
+// priority, non-blocking.
 struct SideStream {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
+    hipStream_t solve = nullptr;
+    hipEvent_t panel = nullptr, solved = nullptr;
 };
 
 SideStream *side_for(hipStream_t caller)
@@ -461,7 +464,10 @@ SideStream *side_for(hipStream_t caller)
     SideStream sd;
     if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
-        hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess) {
+        hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) != hipSuccess ||
+        hipStreamCreateWithFlags(&sd.solve, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.panel, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&sd.solved, hipEventDisableTiming) != hipSuccess) {
         // no lookahead for this stream; remember the failure
         table[key] = SideStream{};
         return nullptr;
@@ -480,10 +486,16 @@ SideStream *side_for(hipStream_t caller)
 // the same columns (the next trailing update).  The two streams write
 // disjoint column ranges and read only finished panels, so the result is the
 // same operations in the same order per entry as without the lookahead.
+// With a solve plan, each finished panel's columns of the forward solve run on
+// a third stream (after an event on the caller's stream marks the panel
+// done) while the next panels are factored; the caller's stream waits for
+// the last segment.  Without side streams the whole solve follows the
+// factorisation on the caller's stream.  The segments are the same
+// operations in the same order as one whole solve.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
                   const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex, bool lookahead,
-                  int extra)
+                  int extra, const SolvePlan *plan)
 {
     const int nparts = np / TB;
     // the INT8 trailing update is built for one rank (OZ_RANK)
@@ -503,6 +515,13 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                                    mask);
             launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, lk, s, mask);
             launch_trsm_panel(A, lda, bstride, rmax, c0, batch, lk, s, mask);
+        }
+        if (plan && sd) {
+            // columns [c, pe) of L are final: their part of the forward solve
+            (void)hipEventRecord(sd->panel, s);
+            (void)hipStreamWaitEvent(sd->solve, sd->panel, 0);
+            launch_solve_segment(A, lda, bstride, np, plan->n, plan->y, lpart, nparts, info, batch,
+                                 plan->out, plan->z, c / TB, pe / TB, sd->solve);
         }
         // right-looking rank-(pe - c) update of the trailing matrix: rows up
         // to rlim, columns [pe, cend); with a border it also covers the
@@ -539,6 +558,13 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             update(pe, cend, s);
     }
     if (pending) (void)hipStreamWaitEvent(s, sd->join, 0);
+    if (plan && sd) {
+        (void)hipEventRecord(sd->solved, sd->solve);
+        (void)hipStreamWaitEvent(s, sd->solved, 0);
+    } else if (plan) {
+        launch_solve_segment(A, lda, bstride, np, plan->n, plan->y, lpart, nparts, info, batch,
+                             plan->out, plan->z, 0, np / TB, s);
+    }
 }
 
 void launch_logdet_sum(const double *lpart, int nparts, int batch, double *logdet, hipStream_t s)

@@ -23,6 +23,7 @@ struct Layout {
     size_t lpart;    // offset of the log-det partials
     size_t info;     // offset of info
     size_t lk;       // diagonal-factor copies for TRSM, batch * 64 * 64 doubles
+    size_t z;        // forward-solve state between solve segments, batch * 2 np doubles
     size_t rhs, x, s; // refinement vectors (mixed mode), batch * 2 np doubles each
     size_t mask;     // per-theta FP64 fallback mask (mixed modes), batch bytes
     size_t oz_sl, oz_ex; // digit slices and row exponents (GP_MIXED)
@@ -43,6 +44,8 @@ bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
     off = align_up(off + sizeof(int32_t) * (size_t)batch);
     L.lk = off;
     off = align_up(off + sizeof(double) * TB * TB * (size_t)batch);
+    L.z = off;
+    off = align_up(off + sizeof(double) * 2 * (size_t)L.np * batch);
     L.rhs = L.x = L.s = L.mask = L.oz_sl = L.oz_ex = off;
     if (prec == GP_MIXED) {
         L.mask = off;
@@ -154,20 +157,17 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
     launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, A, np,
                       L.bstride, np, stream);
     double *lk = (double *)(base + L.lk);
+    // FP64 and GP_MIXED: the forward solves follow the factorisation panel by
+    // panel (solve segments on their own stream), ending with eq. 3-4
+    SolvePlan plan{ds->y, ds->n, (double *)(base + L.z), out};
     factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, prec, false, nullptr,
-                 (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex), lookahead);
-    if (prec == GP_FP64) {
-        launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
-                            stream);
-        return launched();
-    }
+                 (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex), lookahead, 0,
+                 prec == GP_MIXED_FAST ? nullptr : &plan);
+    if (prec == GP_FP64) return launched();
     if (prec == GP_MIXED_FAST)
         refine_solves(A, np, L.bstride, np, ds, theta, batch, lpart, info,
                       (double *)(base + L.rhs), (double *)(base + L.x), (double *)(base + L.s),
                       IR_SWEEPS, out, stream);
-    else
-        launch_solve_reduce(A, np, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
-                            stream);
     // thetas whose mixed result failed (pivot, or refinement in GP_MIXED_FAST)
     // are redone on the FP64 path; their results carry ir_iters = -1
     uint8_t *mask = (uint8_t *)(base + L.mask);

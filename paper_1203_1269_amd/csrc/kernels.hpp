@@ -135,13 +135,27 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
                         int kc0, int K, int batch, hipStream_t s, int prec,
                         const uint8_t *mask = nullptr);
 
+// Forward solves L [a b] = [1 y] and eq. 3-4 run along with the
+// factorisation: the solve of the columns of each finished outer panel (a
+// solve segment) goes to a stream of its own while later panels are
+// factored; z (batch x 2 np doubles) carries the partial solution from one
+// segment to the next, and the last segment writes `out`.
+struct SolvePlan {
+    const double *y;
+    int n;
+    double *z;
+    gp_result *out;
+};
+
 // The whole blocked factorisation (a2) plus log-det partials (a3).  With
 // `bordered`, A has order 2 np and holds [[R, I], [I, 0]]; only the first np
 // columns are factored, which leaves L^-T bottom-left and -R^-1 bottom-right.
+// With a solve plan the forward solves and eq. 3-4 (a4, a6) are done as well.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
                   const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
-                  int32_t *oz_ex = nullptr, bool lookahead = true, int extra = 0);
+                  int32_t *oz_ex = nullptr, bool lookahead = true, int extra = 0,
+                  const SolvePlan *plan = nullptr);
 
 // Predictions: rows np .. np + extra - 1 below the n_pad x n_pad matrix ride
 // through the factorisation as rows below the diagonal (factor_batch with
@@ -214,6 +228,13 @@ void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n
                          const double *y, const double *lpart, int nparts,
                          const int32_t *info, int batch, gp_result *out, hipStream_t s,
                          const uint8_t *mask = nullptr, int ir_tag = 0);
+// Columns [64 ib0, 64 ib1) of the forward solve (right-hand sides from
+// [1 y] when `first`, else from z); the last segment also does the
+// reductions of eq. 3-4 and writes out, the others store the state to z.
+void launch_solve_segment(const double *A, int lda, size_t bstride, int np, int n,
+                          const double *y, const double *lpart, int nparts,
+                          const int32_t *info, int batch, gp_result *out, double *z, int ib0,
+                          int ib1, hipStream_t s);
 
 // mask[b] = 1 for thetas whose mixed-precision result must be recomputed in
 // FP64 (failed pivot or refinement above the FP64 backward-error level).

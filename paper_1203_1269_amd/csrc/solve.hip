@@ -9,6 +9,10 @@
 // contiguous run).  The solution
 // vectors live in LDS (2 n_pad doubles), so n_pad <= 8192.
 // The kernel streams the n^2/2 lower entries of L once: HBM bound.
+// A launch may cover only the column blocks [ib0, ib1) (a solve segment that
+// runs as soon as those columns of L are final): it then starts from, or
+// leaves, the partial solution in z (2 n_pad doubles per matrix), and only
+// the segment that ends at the last block does the reductions.
 #include <math.h>
 
 #include "kernels.hpp"
@@ -32,7 +36,7 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
                          const double *__restrict__ y, const double *__restrict__ lpart,
                          int nparts, const int32_t *__restrict__ info,
                          gp_result *__restrict__ out, const uint8_t *__restrict__ mask,
-                         int ir_tag)
+                         int ir_tag, double *__restrict__ zg, int ib0, int ib1)
 {
     if (mask && !mask[blockIdx.x]) return;
     extern __shared__ double zs[];          // z0[np], z1[np]
@@ -44,13 +48,21 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
     const double *A = A0 + (size_t)b * bstride;
     const int T = np / TB;
 
-    // right-hand sides [1 y] (0 in the padded rows)
-    for (int r = tid; r < np; r += SV_THREADS) {
-        z0[r] = (r < n) ? 1.0 : 0.0;
-        z1[r] = (r < n) ? y[r] : 0.0;
+    double *zb = zg ? zg + (size_t)b * 2 * np : nullptr;
+    if (ib0 == 0) {
+        // right-hand sides [1 y] (0 in the padded rows)
+        for (int r = tid; r < np; r += SV_THREADS) {
+            z0[r] = (r < n) ? 1.0 : 0.0;
+            z1[r] = (r < n) ? y[r] : 0.0;
+        }
+    } else {
+        for (int r = tid; r < np; r += SV_THREADS) {
+            z0[r] = zb[r];
+            z1[r] = zb[np + r];
+        }
     }
     __syncthreads();
-    for (int ib = 0; ib < T; ++ib) {
+    for (int ib = ib0; ib < ib1; ++ib) {
         const int c0 = ib * TB;
         // wave 0: triangular solve of the 64 x 64 diagonal block (lane = row)
         if (wave == 0) {
@@ -90,6 +102,13 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
             }
         }
         __syncthreads();
+    }
+    if (ib1 < T) {   // not the last segment: keep the partial solution
+        for (int r = tid; r < np; r += SV_THREADS) {
+            zb[r] = z0[r];
+            zb[np + r] = z1[r];
+        }
+        return;
     }
 
     // aa = a.a, ab = a.b over the n real rows
@@ -158,7 +177,30 @@ void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n
     const double lower = 0.5 * (double)np * (np + 1);
     ProfScope ps(K_SOLVE_REDUCE, 4.0 * lower * batch, (8.0 * lower + 16.0 * n) * batch, s);
     solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
-                                                       info, out, mask, ir_tag);
+                                                       info, out, mask, ir_tag, nullptr, 0,
+                                                       np / TB);
+}
+
+void launch_solve_segment(const double *A, int lda, size_t bstride, int np, int n,
+                          const double *y, const double *lpart, int nparts,
+                          const int32_t *info, int batch, gp_result *out, double *z, int ib0,
+                          int ib1, hipStream_t s)
+{
+    if (ib1 <= ib0) return;
+    static bool attr_set = false;
+    const size_t shm = (size_t)2 * np * sizeof(double);
+    if (!attr_set) {
+        (void)hipFuncSetAttribute((const void *)solve_reduce_kernel,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(2 * GP_NMAX * sizeof(double)));
+        attr_set = true;
+    }
+    // entries of L read: the lower part of columns [64 ib0, 64 ib1)
+    const double c0 = 64.0 * ib0, c1 = 64.0 * ib1;
+    const double entries = (c1 - c0) * np - 0.5 * (c1 * c1 - c0 * c0) + 0.5 * (c1 - c0);
+    ProfScope ps(K_SOLVE_REDUCE, 4.0 * entries * batch, (8.0 * entries + 32.0 * np) * batch, s);
+    solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
+                                                       info, out, nullptr, 0, z, ib0, ib1);
 }
 
 }  // namespace gpk
