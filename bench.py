@@ -29,7 +29,7 @@ FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
 SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
 
-# HBM traffic of the rank-256 trailing update (syrk_update_kernel) on this
+# HBM traffic of the rank-512 trailing update (syrk_update_kernel) on this
 # workload, from two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) scaled by
 # what the same counters read for a 512 MiB device copy (bench.py
 # --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).

@@ -4,8 +4,8 @@
 // library LU instead, Sec. 3).
 //
 // Two-level blocking:
-//   outer panels of OUTER_NB = 512 columns (256 for GP_MIXED, whose INT8
-//   update is built for rank 256); each is factored by inner steps of TB = 64
+//   outer panels of OUTER_NB = 512 columns (GP_MIXED_RANK = 768 for GP_MIXED,
+//   whose INT8 update is built for that rank); each is factored by inner steps of TB = 64
 //   columns, left-looking inside the panel (update of the 64-column block by
 //   the panel's earlier blocks, POTRF of its 64 x 64 diagonal tile, TRSM of
 //   the rows below it); then the trailing matrix receives one right-looking

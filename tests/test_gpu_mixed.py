@@ -1,10 +1,10 @@
-"""Matched-accuracy mixed mode (GP_MIXED: rank-256 trailing updates on INT8
+"""Matched-accuracy mixed mode (GP_MIXED: rank-768 trailing updates on INT8
 MFMA through an error-free digit splitting of the panel, every other step in
 FP64) against the 80-bit oracle, through the C ABI.
 
 Bar: every output of every theta within max(1e-8, 10 x the FP64 rounding
 spread of two independent FP64 codes for that theta) of the 80-bit oracle,
-info bit-exact.  Shapes span one to several rank-256 updates with ragged
+info bit-exact.  Shapes span one to several rank-768 updates with ragged
 tails; the full-size launch is checked on the sampled thetas of the stored
 oracle values and, at every theta, against the FP64 path.
 """
@@ -58,7 +58,7 @@ def test_mixed_matched_against_oracle(gp, n, d, p, delta, B):
 
 
 def test_mixed_without_trailing_update_is_fp64(gp):
-    """n <= 256: one outer panel, no rank-256 update, so the mixed mode runs
+    """n <= 768: one outer panel, no INT8 update, so the mixed mode runs
     exactly the FP64 kernels: results bitwise the FP64 path's."""
     w = inputs.small_2d()
     ds = gp.Dataset(w.X, w.y, w.p, w.delta)

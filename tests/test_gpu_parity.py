@@ -266,7 +266,7 @@ def test_fullsize_fp64_n4096_d8_sampled(gp):
 # conditioning of R.
 
 def test_mixed_fast_single_panel_factor_is_fp64(gp):
-    """Without a rank-256 trailing update (n <= 256) the mixed mode factors
+    """Without a trailing update (n <= 512, one outer panel) the mixed mode factors
     with the FP64 kernels only: log|R| is bitwise the FP64 one, and the
     refined mu and sigma2 stay within the FP64 tolerance."""
     w = inputs.small_2d()
