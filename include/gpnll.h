@@ -23,11 +23,12 @@
  *   - Calls are asynchronous and stream-ordered on `stream`; the returned
  *     status reports argument and launch errors only and never waits.  The
  *     factorisation overlaps its trailing updates with the next panel on a
- *     second stream: the library creates one such stream (default priority)
- *     and two events per (device, caller stream) on first use and keeps them
- *     until the process ends; the work on it is joined back into `stream`
- *     before the call's last kernel, so the call still behaves as ordered on
- *     `stream`.  Calls that share a stream must not be issued from several
+ *     second stream, and runs the forward solve of each finished panel on a
+ *     third: the library creates these two streams (default priority) and
+ *     five events per (device, caller stream) on first use and keeps them
+ *     until the process ends; their work is joined back into `stream` before
+ *     the call returns its last kernel, so the call still behaves as ordered
+ *     on `stream`.  Calls that share a stream must not be issued from several
  *     host threads at the same time.
  *   - Numerical status is per theta, written on the device in
  *     gp_result.info (one bad theta never fails the batch):
