@@ -25,9 +25,9 @@
  *     factorisation overlaps its trailing updates with the next panel on a
  *     second stream, and runs the forward solve of each finished panel on a
  *     third: the library creates these two streams (default priority) and
- *     five events per (device, caller stream) on first use and keeps them
+ *     four events per (device, caller stream) on first use and keeps them
  *     until the process ends; their work is joined back into `stream` before
- *     the call returns its last kernel, so the call still behaves as ordered
+ *     the call's last kernel, so the call still behaves as ordered
  *     on `stream`.  Calls that share a stream must not be issued from several
  *     host threads at the same time.
  *   - Numerical status is per theta, written on the device in
