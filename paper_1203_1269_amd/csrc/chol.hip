@@ -122,16 +122,16 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
 // ---------------------------------------------------------------------------
 // TRSM: rows below the diagonal tile, X L_kk' = A, i.e. per row
 // x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj, right-looking over j.  One lane
-// per row with its 64 entries in registers.  L_kk is read from the
-// read-only copy written by potrf_diag: every lane of a wave needs the same
-// L value at the same time, so the reads are scalar loads into SGPRs and each
-// FP64 FMA takes its L operand from an SGPR (no LDS traffic).  The diagonal
-// of the copy holds 1 / L_jj.
+// per row with its 64 entries in registers.  The workgroup copies L_kk (the
+// copy written by potrf_diag, diagonal holding 1 / L_jj) into LDS once; every
+// lane of a wave then needs the same L value at the same time, an LDS
+// broadcast.  (Scalar loads of L straight from memory, each wave fetching
+// the 32 KiB itself, measured 0.8% slower overall, bitwise the same.)
 
 constexpr int TR_THREADS = 256;
 constexpr int TR_ROWS = TR_THREADS;
 #ifndef TR_MIN_BLOCKS
-#define TR_MIN_BLOCKS 3
+#define TR_MIN_BLOCKS 2
 #endif
 
 __global__ __launch_bounds__(TR_THREADS, TR_MIN_BLOCKS)
@@ -139,11 +139,13 @@ void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
                        const double *__restrict__ lk0, const uint8_t *__restrict__ mask)
 {
     const int b = blockIdx.y;
-    if (mask && !mask[b]) return;
+    if (mask && !mask[b]) return;   // uniform over the workgroup
     double *A = A0 + (size_t)b * bstride;
-    const double *lk = lk0 + (size_t)b * TB * TB;
+    __shared__ double lk[TB * TB];
+    for (int e = threadIdx.x; e < TB * TB; e += TR_THREADS) lk[e] = lk0[(size_t)b * TB * TB + e];
+    __syncthreads();
     const int row = c0 + TB + blockIdx.x * TR_ROWS + threadIdx.x;
-    if (row >= np) return;
+    if (row >= np) return;   // after the only barrier
     double x[TB];
     {
         const double *p = A + (size_t)row + (size_t)c0 * lda;
@@ -157,7 +159,7 @@ void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
         for (int c = j + 1; c < TB; ++c) x[c] = fma(-x[j], lk[j * TB + c], x[c]);
     }
     // recompute the store addresses rather than keeping 64 of them live, so
-    // that two waves fit per SIMD (the scalar-load latency is then hidden)
+    // that two waves fit per SIMD
     int r2 = row;
     asm volatile("" : "+v"(r2));
     double *q = A + (size_t)r2 + (size_t)c0 * lda;
