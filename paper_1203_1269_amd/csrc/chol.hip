@@ -228,14 +228,18 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
     const double *pa = A + (size_t)(r0 + pli) + (size_t)(kc0 + lk) * lda;
     const double *pb = A + (size_t)(c0 + li) + (size_t)(kc0 + lk) * lda;
     const size_t step4 = (size_t)4 * lda;
+    // (in set order, before the loads of C: the loop then finds set 0's
+    // fragments the oldest loads in flight on entry as on every later trip)
     double fa[SY_NSETS][4], fb[SY_NSETS][4];
 #pragma unroll
-    for (int st = 0; st < SY_NSETS; ++st)
+    for (int st = 0; st < SY_NSETS; ++st) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
             fa[st][q] = pa[st * step4 + 16 * q];
             fb[st][q] = pb[st * step4 + 16 * q];
         }
+        __builtin_amdgcn_sched_barrier(0);
+    }
 
     // accumulators start at -C and gather +A(r,k) A(c,k): no per-step negation
     dbl4 acc[4][4];
@@ -251,7 +255,10 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
 
     // K is a multiple of 4 SY_NSETS: SY_NSETS k-steps per trip, each
     // fragment set reloaded for the trip after this one right after its
-    // MFMAs were issued (prefetch distance SY_NSETS k-steps)
+    // MFMAs were issued (prefetch distance SY_NSETS k-steps).  The reloads
+    // are unconditional (in the last trip they re-read the set just used, in
+    // bounds and unused), so every trip issues the same loads and each set
+    // waits only for its own fragments, not for the whole prefetch queue.
     for (int kk = 0; kk < K; kk += 4 * SY_NSETS) {
 #pragma unroll
         for (int st = 0; st < SY_NSETS; ++st) {
@@ -261,13 +268,19 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
                 for (int cb = 0; cb < 4; ++cb)
                     acc[rb][cb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[st][rb], fb[st][cb],
                                                                        acc[rb][cb], 0, 0, 0);
-            if (kk + 4 * (SY_NSETS + st) < K) {
+            const size_t nx = (kk + 4 * (SY_NSETS + st) < K) ? (size_t)(SY_NSETS + st) * step4
+                                                              : (size_t)st * step4;
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    fa[st][q] = pa[(SY_NSETS + st) * step4 + 16 * q];
-                    fb[st][q] = pb[(SY_NSETS + st) * step4 + 16 * q];
-                }
+            for (int q = 0; q < 4; ++q) {
+                fa[st][q] = pa[nx + 16 * q];
+                fb[st][q] = pb[nx + 16 * q];
             }
+            // keeps these loads here: without the memory barrier the compiler
+            // merges them with the prologue loads into one load at the top of
+            // the loop, right before the first use; without the scheduling
+            // barrier it moves them below the later sets' MFMAs
+            asm volatile("" ::: "memory");
+            __builtin_amdgcn_sched_barrier(0);
         }
         pa += SY_NSETS * step4;
         pb += SY_NSETS * step4;
