@@ -336,8 +336,10 @@ void syrk_update_f32_kernel(double *__restrict__ A0, int lda, size_t bstride, in
     double a0[4], b0[4], a1[4], b1[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
+    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
+    __builtin_amdgcn_sched_barrier(0);
 
     flt4 acc[4][4];
 #pragma unroll
@@ -354,12 +356,14 @@ void syrk_update_f32_kernel(double *__restrict__ A0, int lda, size_t bstride, in
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb)
                 acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[rb], fb[cb], acc[rb][cb], 0, 0, 0);
-        pa += 2 * step4;
-        pb += 2 * step4;
-        if (kk + 8 < K) {
+        // the reloads are unconditional (in the last trip they re-read the
+        // fragments just used, in bounds and unused) and pinned in place, so
+        // each half-trip waits for its own loads only (as in the FP64 kernel)
+        const size_t n0 = (kk + 8 < K) ? 2 * step4 : 0, n1 = (kk + 12 < K) ? 2 * step4 : 0;
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { a0[q] = pa[16 * q]; b0[q] = pb[16 * q]; }
-        }
+        for (int q = 0; q < 4; ++q) { a0[q] = pa[n0 + 16 * q]; b0[q] = pb[n0 + 16 * q]; }
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int q = 0; q < 4; ++q) { fa[q] = (float)a1[q]; fb[q] = (float)b1[q]; }
 #pragma unroll
@@ -367,19 +371,31 @@ void syrk_update_f32_kernel(double *__restrict__ A0, int lda, size_t bstride, in
 #pragma unroll
             for (int cb = 0; cb < 4; ++cb)
                 acc[rb][cb] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[rb], fb[cb], acc[rb][cb], 0, 0, 0);
-        if (kk + 12 < K) {
 #pragma unroll
-            for (int q = 0; q < 4; ++q) { a1[q] = pa[step4 + 16 * q]; b1[q] = pb[step4 + 16 * q]; }
-        }
+        for (int q = 0; q < 4; ++q) { a1[q] = pa[n1 + step4 + 16 * q]; b1[q] = pb[n1 + step4 + 16 * q]; }
+        asm volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        pa += 2 * step4;
+        pb += 2 * step4;
     }
 
+    // C is read whole before the first store (the stores might alias later
+    // loads as far as the compiler knows, which would serialise them)
+    dbl2 cv[4][4][2];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 4; ++cb) {
+            const double *p = A + (size_t)(r0 + 16 * rb + 4 * lk) + (size_t)(c0 + 16 * cb + li) * lda;
+            cv[rb][cb][0] = *(const dbl2 *)p;
+            cv[rb][cb][1] = *(const dbl2 *)(p + 2);
+        }
 #pragma unroll
     for (int rb = 0; rb < 4; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
             double *p = A + (size_t)(r0 + 16 * rb + 4 * lk) + (size_t)(c0 + 16 * cb + li) * lda;
-            dbl2 lo = *(const dbl2 *)p;
-            dbl2 hi = *(const dbl2 *)(p + 2);
+            const dbl2 lo = cv[rb][cb][0], hi = cv[rb][cb][1];
             const flt4 v = acc[rb][cb];
             *(dbl2 *)p = (dbl2){lo.x - (double)v.x, lo.y - (double)v.y};
             *(dbl2 *)(p + 2) = (dbl2){hi.x - (double)v.z, hi.y - (double)v.w};
