@@ -35,8 +35,8 @@ SYRK_SRC = os.path.join(ROOT, "paper_1203_1269_amd", "csrc", "chol.hip")
 # --copy-calibration: FETCH_SIZE reads 0.5x the bytes copied, WRITE_SIZE 1.0x).
 # Valid only for the kernel and launch loop it was taken on: reported as null
 # once the sha256 of their source differs.
-SYRK_TRAFFIC = {"kernel_sha256": "99e46dab59463204494ed62cded5609cc2fa0fd09729b119ca0e46f58ede2b65",
-                "bytes_per_launch": (2.0 * 3.33056e7 + 1.0 * 1.88088e7) / 13 * 1024}
+SYRK_TRAFFIC = {"kernel_sha256": "0eae681ab8c5b2740e31e95b06ea96524cfad3decdcb6a7a63e1f413f583b320",
+                "bytes_per_launch": (2.0 * 5.32033e7 + 1.0 * 1.88089e7) / 13 * 1024}
 
 
 def syrk_kernel_text():
@@ -44,7 +44,8 @@ def syrk_kernel_text():
     launches it (the launch shapes decide the per-launch traffic)."""
     with open(SYRK_SRC) as f:
         src = f.read()
-    parts = []
+    parts = [line for line in src.splitlines(keepends=True)
+             if line.startswith(("#define SY_", "constexpr int SY_"))]
     for start in ("void syrk_update_kernel(", "void factor_batch("):
         i = src.index(start)
         parts.append(src[i:src.index("\n}\n", i) + 3])

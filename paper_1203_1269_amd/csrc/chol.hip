@@ -189,7 +189,7 @@ void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
 constexpr int SY_THREADS = 256;
 constexpr int NXCD = 8;
 #ifndef SY_NSETS
-#define SY_NSETS 4   // fragment sets in flight (prefetch distance in k-steps of 4)
+#define SY_NSETS 2   // fragment sets in flight (prefetch distance in k-steps of 4)
 #endif
 
 // WR x WC waves of 64 x 64: <2,2> = 128 x 128 tiles over a lower-triangular
