@@ -181,7 +181,7 @@ static void fill_nan(double *out)
  * factor, a = L^-1 1 and b = L^-1 y, then eq. 3 and eq. 4. */
 static int eval_one(int n, int d, const double *X, const double *y,
                     const double *theta_in, REAL p, int fam, REAL delta,
-                    double *out, REAL *work, REAL *mu_out)
+                    double *out, REAL *work, REAL *mu_out, REAL *sigma2_out)
 {
     if (!theta_ok(d, theta_in)) { fill_nan(out); return -3; }
     REAL theta[64];
@@ -213,6 +213,7 @@ static int eval_one(int n, int d, const double *X, const double *y,
     for (int i = 0; i < n; ++i) { REAL r = b[i] - mu * a[i]; Q += r * r; }
     REAL sigma2 = Q / (REAL)n;
     if (mu_out) *mu_out = mu;
+    if (sigma2_out) *sigma2_out = sigma2;
 
     out[0] = (double)logdet;
     out[1] = (double)mu;
@@ -287,7 +288,7 @@ int SFX(orc_nll_batch)(int n, int d, const double *X, const double *y,
 #pragma omp for schedule(dynamic, 1)
             for (int t = 0; t < B; ++t)
                 info[t] = eval_one(n, d, X, y, theta + (size_t)t * d, (REAL)p, fam,
-                                   (REAL)delta, out + (size_t)t * ORC_NOUT, work, NULL);
+                                   (REAL)delta, out + (size_t)t * ORC_NOUT, work, NULL, NULL);
             free(work);
         }
     }
@@ -332,7 +333,7 @@ int SFX(orc_grad_batch)(int n, int d, const double *X, const double *y,
                 REAL *v = work + 3 * nn;
                 REAL *z = v + n, *w = z + n, *alpha = w + n;
                 REAL mu = 0;
-                int inf = eval_one(n, d, X, y, th_in, (REAL)p, fam, (REAL)delta, o, work, &mu);
+                int inf = eval_one(n, d, X, y, th_in, (REAL)p, fam, (REAL)delta, o, work, &mu, NULL);
                 info[t] = inf;
                 if (inf != 0) {
                     for (int k = 0; k < d; ++k) g[k] = NAN;
@@ -394,8 +395,8 @@ int SFX(orc_predict)(int n, int d, const double *X, const double *y, const doubl
     size_t nn = (size_t)n * n;
     REAL *work = (REAL *)malloc(sizeof(REAL) * (2 * nn + 8 * (size_t)n));
     if (!work) return -101;
-    REAL mu = 0;
-    int info = eval_one(n, d, X, y, theta_in, p, fam, delta, fit, work, &mu);
+    REAL mu = 0, sigma2 = 0;
+    int info = eval_one(n, d, X, y, theta_in, p, fam, delta, fit, work, &mu, &sigma2);
     if (info != 0 && info != -1) {
         for (int j = 0; j < N; ++j) mean[j] = mse[j] = NAN;
         free(work);
@@ -417,7 +418,6 @@ int SFX(orc_predict)(int n, int d, const double *X, const double *y, const doubl
     back_solve(n, L, z, one_inv);
     REAL oRo = 0;
     for (int i = 0; i < n; ++i) oRo += one_inv[i];
-    const REAL sigma2 = (REAL)fit[2];
     for (int j = 0; j < N; ++j) {
         for (int i = 0; i < n; ++i) {
             REAL prod = 1;

@@ -3,8 +3,11 @@
 Calls only the CPU oracle (80-bit and FP64 builds, plus LAPACK on the
 oracle's R to measure the FP64 rounding spread) on the seeded inputs of
 paper_1203_1269_amd.inputs; the GPU path is not involved.  Usage:
-    python tests/golden/make_expected.py fp64_n4096_d8
+    python tests/golden/make_expected.py fp64_n4096_d8 all
+    python tests/golden/make_expected.py mixed_n8192_d10 all
+    python tests/golden/make_expected.py grad_n4096_d6 all
     python tests/golden/make_expected.py pred_n4096_d8 2
+("all": every theta of the workload; a number k: k sampled thetas.)
 """
 import json
 import os
@@ -31,7 +34,10 @@ WORKLOADS = {
 
 
 def sample_indices(theta, k):
-    """The theta with the smallest and the largest norm plus evenly spaced others."""
+    """The theta with the smallest and the largest norm plus evenly spaced
+    others; every theta when k covers the batch."""
+    if k >= theta.shape[0]:
+        return list(range(theta.shape[0]))
     norms = np.linalg.norm(np.log(theta), axis=1)
     idx = {int(np.argmin(np.sum(theta, axis=1))), int(np.argmax(np.sum(theta, axis=1)))}
     for q in np.linspace(0, theta.shape[0] - 1, k):
@@ -118,4 +124,5 @@ def main(name, k=4):
 
 
 if __name__ == "__main__":
-    main(sys.argv[1], int(sys.argv[2]) if len(sys.argv) > 2 else 4)
+    arg = sys.argv[2] if len(sys.argv) > 2 else "4"
+    main(sys.argv[1], 1 << 30 if arg == "all" else int(arg))
