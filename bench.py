@@ -60,7 +60,8 @@ def parse():
     ap.add_argument("--batch", type=int, default=128)
     ap.add_argument("--n", type=int, default=4096)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision leg")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision legs")
+    ap.add_argument("--no-mixed-fast", action="store_true", help="skip the FP32-update mixed leg")
     ap.add_argument("--no-serving", action="store_true", help="skip the request-server leg")
     ap.add_argument("--no-large", action="store_true", help="skip the n=8192 leg")
     ap.add_argument("--no-grad", action="store_true", help="skip the gradient / L-BFGS leg")
@@ -73,7 +74,9 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 512 MiB device-to-device copy first (counter calibration)")
     ap.add_argument("--cpu-threads", type=int, default=0,
-                    help="oracle threads (default: min(16, available cores))")
+                    help="oracle threads (default: every core this process may run on)")
+    ap.add_argument("--prof-steps", type=int, default=3,
+                    help="instrumented steps (per-launch HIP events) after the timed ones")
     return ap.parse_args()
 
 
@@ -243,7 +246,7 @@ def serving_leg(args, dev):
 PRECS = ("fp64", "mixed", "mixed_fast")
 
 
-def time_batch(binding, torch, ds, theta, ws, prec, steps, warmup, profile=True):
+def time_batch(binding, torch, ds, theta, ws, prec, steps, warmup, profile=False):
     """`warmup` untimed then `steps` timed gp_nll_batch calls on the current
     stream; returns (seconds, per-kernel stats of the timed calls, results)."""
     B = theta.shape[0]
@@ -275,23 +278,71 @@ def rel_errs(res, ref, y):
                             np.maximum(np.abs(ref[k][ok]), sc[k]))) for k in sc}, ok
 
 
-def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps):
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+FP64_FLOOR, MATCH_FLOOR = 1e-10, 1e-8
+
+
+def load_golden(name):
+    """Stored oracle values (80-bit and FP64 builds of the C oracle, LAPACK
+    spread) for thetas of a full-size workload, written by
+    tests/golden/make_expected.py; None when absent."""
+    path = os.path.join(GOLDEN, f"{name}_expected.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        return json.load(f)
+
+
+def oracle_check(res, exp, y, floor):
+    """Largest relative error per output against the stored 80-bit oracle
+    values, and how many stored thetas lie within their bar
+    max(floor, 10 x the FP64 rounding spread of that theta)."""
+    import numpy as np
+    if exp is None:
+        return None
+    sc = {"logdet": 1.0, "nll": 1.0, "mu": float(np.std(y)), "sigma2": 0.0}
+    worst = {k: 0.0 for k in sc}
+    n = within = 0
+    for rec in exp["samples"]:
+        t = rec["index"]
+        n += 1
+        ok = int(res["info"][t]) == rec["info"]
+        if rec["info"] != 0:
+            within += ok
+            continue
+        for k in sc:
+            ref = rec["f80"][k]
+            e = abs(float(res[k][t]) - ref) / max(abs(ref), sc[k])
+            worst[k] = max(worst[k], e)
+            tol = max(floor, 10 * max(rec["err64"][k], rec["err64_lapack"][k]))
+            ok = ok and e <= tol
+        within += ok
+    return {"thetas": n, "max_rel_err": worst, "within_bar": within, "floor": floor}
+
+
+def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps, kst_steps=1):
+    """A mixed mode's timing (dt over `steps` steps) against the FP64 path,
+    its largest differences from the FP64 GPU results, and the kernel table
+    of its instrumented pass (`kst` over `kst_steps` steps)."""
     errs, ok = rel_errs(res, res64, w.y)
     out = {"prec": prec, "value": w.B * steps / dt, "ms_per_step": dt / steps * 1e3,
            "speedup_vs_fp64": dt64 / dt, "max_rel_err_vs_fp64_gpu": errs,
            "results_ok": int((res["info"] == 0).sum()),
            "results_recomputed_fp64": int((res["ir_iters"] == -1).sum()),
            "matched_1e-8": bool(errs["nll"] is not None and errs["nll"] <= 1e-8 and ok.all()),
-           "kernels_ms_per_step": {k: v["ms"] / steps for k, v in kst.items()}}
+           "kernels_ms_per_step": {k: v["ms"] / kst_steps for k, v in kst.items()}}
     if prec == "mixed":
-        sy = kst.get("syrk_update_i8", {"flops": 0.0, "ms": 1.0})
-        out["trailing_update_fp64_equiv_tflops"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12
-        # INT8 MFMA operations actually issued: S(S+1)/2 digit pairs per FP64 product
+        # INT8 MFMA operations issued per FP64 product: 16 modular products
+        # (CRT update), or S(S+1)/2 digit pairs (digit update)
         from paper_1203_1269_amd import binding
-        S = binding.header_constant("GP_MIXED_DIGITS")
-        pairs = S * (S + 1) // 2
-        out["digits"] = S
-        out["trailing_update_int8_tops"] = pairs * sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+        if "syrk_update_crt" in kst:
+            sy, per, out["int8_scheme"] = kst["syrk_update_crt"], 16, "crt16"
+        else:
+            S = binding.header_constant("GP_MIXED_DIGITS")
+            sy = kst.get("syrk_update_i8", {"flops": 0.0, "ms": 1.0})
+            per, out["int8_scheme"] = S * (S + 1) // 2, f"digits{S}"
+        out["trailing_update_fp64_equiv_tflops"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12
+        out["trailing_update_int8_tops"] = per * sy["flops"] / (sy["ms"] * 1e-3) / 1e12
         out["trailing_update_frac_of_int8_peak"] = out["trailing_update_int8_tops"] / 5000.0
     else:
         sy = kst.get("syrk_update_f32", {"flops": 0.0, "ms": 1.0})
@@ -300,26 +351,35 @@ def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps):
 
 
 def large_leg(args, dev):
-    """n=8192, d=10, p=2, 32 thetas: FP64 and matched-accuracy mixed."""
+    """n=8192, d=10, p=2, 32 thetas: FP64, matched-accuracy mixed and the FP32
+    mode, each against the stored oracle values of this workload."""
     import torch
     from paper_1203_1269_amd import binding, inputs
     w = inputs.mixed_at_scale()
     ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
     theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
-    ws = binding.alloc_workspace(max(binding.workspace_bytes(w.n, w.d, w.B, p) for p in
-                                     ("fp64", "mixed")), dev)
+    ws = binding.alloc_workspace(max(binding.workspace_bytes(w.n, w.d, w.B, p) for p in PRECS), dev)
     steps = max(1, args.steps // 3)
-    dt64, k64, r64 = time_batch(binding, torch, ds, theta, ws, "fp64", steps, 1)
-    dtm, km, rm = time_batch(binding, torch, ds, theta, ws, "mixed", steps, 1)
+    gold = load_golden(w.name)
+    dt64, _, r64 = time_batch(binding, torch, ds, theta, ws, "fp64", steps, 1)
+    _, k64, _ = time_batch(binding, torch, ds, theta, ws, "fp64", 1, 0, profile=True)
+    dtm, _, rm = time_batch(binding, torch, ds, theta, ws, "mixed", steps, 1)
+    _, km, _ = time_batch(binding, torch, ds, theta, ws, "mixed", 1, 0, profile=True)
+    dtf, _, rf = time_batch(binding, torch, ds, theta, ws, "mixed_fast", 1, 1)
     del ws
     torch.cuda.empty_cache()
     sy = k64["syrk_update"]
-    return {"workload": w.name, "n": w.n, "d": w.d, "batch": w.B, "p": w.p, "delta": w.delta,
-            "steps": steps, "fp64_evals_per_s": w.B * steps / dt64,
-            "fp64_syrk_update_frac_of_peak": sy["flops"] / (sy["ms"] * 1e-3) / FP64_MFMA_PEAK,
-            "fp64_factorization_frac_of_peak": w.n ** 3 / 3.0 * w.B * steps / dt64 / FP64_MFMA_PEAK,
-            "fp64_results_ok": int((r64["info"] == 0).sum()),
-            "mixed": mixed_summary("mixed", dtm, km, rm, dt64, r64, w, steps)}
+    out = {"workload": w.name, "n": w.n, "d": w.d, "batch": w.B, "p": w.p, "delta": w.delta,
+           "steps": steps, "fp64_evals_per_s": w.B * steps / dt64,
+           "fp64_syrk_update_frac_of_peak": sy["flops"] / (sy["ms"] * 1e-3) / FP64_MFMA_PEAK,
+           "fp64_factorization_frac_of_peak": w.n ** 3 / 3.0 * w.B * steps / dt64 / FP64_MFMA_PEAK,
+           "fp64_results_ok": int((r64["info"] == 0).sum()),
+           "fp64_vs_oracle": oracle_check(r64, gold, w.y, FP64_FLOOR),
+           "mixed": mixed_summary("mixed", dtm, km, rm, dt64, r64, w, steps),
+           "mixed_fast": mixed_summary("mixed_fast", dtf * steps, {}, rf, dt64, r64, w, steps)}
+    out["mixed"]["vs_oracle"] = oracle_check(rm, gold, w.y, MATCH_FLOOR)
+    out["mixed_fast"]["vs_oracle"] = oracle_check(rf, gold, w.y, MATCH_FLOOR)
+    return out
 
 
 def gradient_leg(args, dev):
@@ -469,14 +529,38 @@ def main():
     w = inputs.fp64_at_scale(n=args.n, B=args.batch)
     ds = binding.Dataset(w.X, w.y, w.p, w.delta, device=dev)
     theta = torch.as_tensor(w.theta, dtype=torch.float64, device=dev).contiguous()
-    precs = ("fp64",) if args.no_mixed else PRECS
+    precs = ("fp64",) if args.no_mixed else (("fp64", "mixed") if args.no_mixed_fast else PRECS)
     ws = binding.alloc_workspace(max(binding.workspace_bytes(w.n, w.d, w.B, p) for p in precs), dev)
 
     runs = {}
-    for prec in reversed(precs):   # FP64 last: its line is the one profiled alone
-        runs[prec] = time_batch(binding, torch, ds, theta, ws, prec, args.steps, args.warmup)
-    dt, kstats, res64 = runs["fp64"]
-    mixed = {p: mixed_summary(p, *runs[p], dt, res64, w, args.steps) for p in precs if p != "fp64"}
+    for prec in reversed(precs):   # FP64 last
+        # the FP32 mode is reported for its errors, not timed at length
+        steps = args.steps if prec != "mixed_fast" else max(1, args.steps // 4)
+        runs[prec] = time_batch(binding, torch, ds, theta, ws, prec, steps, args.warmup)
+    # an instrumented pass after the timed steps: the library records HIP
+    # events around every launch on the stream it runs on; these give the
+    # per-kernel table and the roofline (the timed steps above run without)
+    prof = {}
+    for prec in precs:
+        if prec != "mixed_fast":
+            _, prof[prec], _ = time_batch(binding, torch, ds, theta, ws, prec, args.prof_steps, 0,
+                                          profile=True)
+    dt, _, res64 = runs["fp64"]
+    kstats = prof["fp64"]
+    gold = load_golden(w.name) if (args.n == 4096 and args.batch == 128) else None
+    mixed = {}
+    for p in precs:
+        if p == "fp64":
+            continue
+        dtp, _, resp = runs[p]
+        steps = args.steps if p != "mixed_fast" else max(1, args.steps // 4)
+        mixed[p] = mixed_summary(p, dtp * args.steps / steps, prof.get(p, {}), resp, dt, res64, w,
+                                 args.steps, args.prof_steps)
+        mixed[p]["vs_oracle"] = oracle_check(resp, gold, w.y, MATCH_FLOOR)
+        if p == "mixed" and mixed[p]["vs_oracle"] is not None:
+            vo = mixed[p]["vs_oracle"]
+            mixed[p]["matched_1e-8_vs_oracle"] = vo["within_bar"] == vo["thetas"]
+    oracle64 = oracle_check(res64, gold, w.y, FP64_FLOOR)
 
     n_ok = int((res64["info"] == 0).sum())
     evals = w.B * args.steps / dt
@@ -485,17 +569,18 @@ def main():
     sy = kstats["syrk_update"]
     achieved = sy["flops"] / (sy["ms"] * 1e-3)
     factor_flops = w.n ** 3 / 3.0
-    # per kernel: event time per step, algorithmic FLOPs and bytes per step,
-    # and the rates they imply (bytes against the 8 TB/s HBM peak); kernels
-    # of the factorisation overlap each other (lookahead), so their event
-    # times include that sharing
-    kernels = {k: {"ms_per_step": v["ms"] / args.steps, "launches_per_step": v["launches"] / args.steps,
-                   "gflop_per_step": v["flops"] / args.steps / 1e9,
-                   "gbyte_per_step": v["bytes"] / args.steps / 1e9,
+    # per kernel (instrumented pass): event time per step, algorithmic FLOPs
+    # and bytes per step, and the rates they imply (bytes against the 8 TB/s
+    # HBM peak); kernels of the factorisation overlap each other
+    # (lookahead), so their event times include that sharing
+    ps = args.prof_steps
+    kernels = {k: {"ms_per_step": v["ms"] / ps, "launches_per_step": v["launches"] / ps,
+                   "gflop_per_step": v["flops"] / ps / 1e9,
+                   "gbyte_per_step": v["bytes"] / ps / 1e9,
                    "tflop_per_s": v["flops"] / (v["ms"] * 1e-3) / 1e12 if v["ms"] > 0 else None,
-                   "gbyte_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None,
-                   "frac_hbm_peak": v["bytes"] / (v["ms"] * 1e-3) / HBM_PEAK if v["ms"] > 0 else None}
+                   "gbyte_per_s": v["bytes"] / (v["ms"] * 1e-3) / 1e9 if v["ms"] > 0 else None}
                for k, v in kstats.items()}
+    mx = mixed.get("mixed")
     line = {
         "metric": METRIC,
         "value": evals,
@@ -511,10 +596,16 @@ def main():
         "data": "synthetic",
         "config": {"workload": w.name, "n": w.n, "d": w.d, "batch": w.B, "p": w.p,
                    "delta": w.delta, "prec": "fp64", "seed": w.seed},
+        "mixed_value": mx["value"] if mx else None,
+        "mixed_vs_fp64": mx["speedup_vs_fp64"] if mx else None,
+        "oracle_fp64": oracle64,
+        "oracle_mixed": mx["vs_oracle"] if mx else None,
         "roofline": {"bound": "mfma", "kernel": "syrk_update", "achieved": achieved / 1e12,
                      "peak": FP64_MFMA_PEAK / 1e12, "unit": "TFLOP/s",
                      "frac": achieved / FP64_MFMA_PEAK, "traffic": syrk_traffic(),
-                     "traffic_unit": "bytes per launch"},
+                     "traffic_unit": "bytes per launch",
+                     "measured": f"HIP events around each launch, {ps} instrumented steps after "
+                                 "the timed ones"},
         "factorization_frac_of_fp64_peak": factor_flops * evals / FP64_MFMA_PEAK,
         "results_ok": n_ok,
         "kernels": kernels,
@@ -536,9 +627,22 @@ def main():
         line["multi_dataset"] = multi_leg(args, dev)
         line["serving"] = serving_leg(args, dev)
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, len(os.sched_getaffinity(0)))
+        threads = args.cpu_threads or len(os.sched_getaffinity(0))
         line["cpu_baseline"] = cpu_baseline(w, threads)
+        line["cpu_baseline"]["nproc"] = os.cpu_count()
         line["cpu_lapack"] = cpu_lapack_baseline(w, threads)
+    # the headline comparison again at the end of the line, where a
+    # truncated capture of the output still shows it
+    line["summary"] = {
+        "fp64_evals_per_s": evals,
+        "mixed_evals_per_s": mx["value"] if mx else None,
+        "mixed_vs_fp64": mx["speedup_vs_fp64"] if mx else None,
+        "fp64_max_rel_err_vs_oracle": oracle64["max_rel_err"] if oracle64 else None,
+        "mixed_max_rel_err_vs_oracle": (mx["vs_oracle"] or {}).get("max_rel_err") if mx else None,
+        "mixed_matched_1e-8_vs_oracle": mx.get("matched_1e-8_vs_oracle") if mx else None,
+        "n8192_mixed_vs_fp64": (line.get("large_n8192") or {}).get("mixed", {}).get(
+            "speedup_vs_fp64"),
+    }
     print(json.dumps(line), flush=True)
 
 

@@ -26,9 +26,10 @@
  *     second stream, and runs the forward solve of each finished panel on a
  *     third: the library creates these two streams (default priority) and
  *     four events per (device, caller stream) on first use and keeps them
- *     until the process ends; their work is joined back into `stream` before
- *     the call's last kernel, so the call still behaves as ordered
- *     on `stream`.  Calls that share a stream must not be issued from several
+ *     until the process ends (for at most 64 caller streams; calls on
+ *     further streams factor without the lookahead, with the same results);
+ *     their work is joined back into `stream` before the call's last
+ *     kernel, so the call still behaves as ordered on `stream`.  Calls that share a stream must not be issued from several
  *     host threads at the same time.
  *   - Numerical status is per theta, written on the device in
  *     gp_result.info (one bad theta never fails the batch):
@@ -60,7 +61,8 @@ extern "C" {
 #define GP_NMAX 8192
 #define GP_DMAX 32
 #define GP_BATCH_MAX 65535
-#define GP_MIXED_DIGITS 8   /* digits per panel entry in GP_MIXED */
+#define GP_MIXED_MODULI 16  /* INT8 moduli of the GP_MIXED trailing update */
+#define GP_MIXED_DIGITS 8   /* digits per panel entry of the digit-split update */
 #define GP_MIXED_RANK 768   /* rank of the GP_MIXED trailing updates (outer panel width) */
 
 typedef enum {
@@ -73,18 +75,21 @@ typedef enum {
 typedef enum {
     GP_FP64 = 0,         /* every step in FP64 (FP64 MFMA for the trailing updates) */
     GP_MIXED = 1,        /* matched accuracy: the rank-768 trailing updates
-                            C -= P P^T run on INT8 MFMA through an error-free
-                            splitting of P (per-row power-of-two scale,
-                            GP_MIXED_DIGITS signed 7-bit digits, the digit
-                            pairs of combined weight >= 2^-(7 GP_MIXED_DIGITS
-                            + 7) accumulated exactly in INT32 and combined in
-                            FP64); every other step in FP64.  The update
-                            carries about 7 GP_MIXED_DIGITS significant bits
-                            relative to the row scales (56, as many as the
-                            FP64 update): -2logL and log|R| agree with the
-                            FP64 path well within 1e-8 relative.  A theta
-                            whose factorisation loses positive definiteness
-                            is recomputed on the FP64 path within the same
+                            C -= P P^T run on INT8 MFMA by modular
+                            arithmetic: each row of P is rounded to a
+                            fixed-point integer (per-row power-of-two scale,
+                            56 fraction bits at rank 768), the integer
+                            product is formed exactly modulo
+                            GP_MIXED_MODULI pairwise coprime moduli <= 256
+                            (one INT8 product with exact INT32 accumulation
+                            per modulus) and recovered by the Chinese
+                            remainder theorem in FP64; every other step in
+                            FP64.  The update is as accurate as the FP64 one
+                            (error below K 2^-56 of the row scales):
+                            -2logL and log|R| agree with the FP64 path well
+                            within 1e-8 relative.  A theta whose
+                            factorisation loses positive definiteness is
+                            recomputed on the FP64 path within the same
                             call (gp_result.ir_iters = -1). */
     GP_MIXED_FAST = 2    /* rank-512 trailing updates on FP32 MFMA with FP32
                             accumulation; correlation build, diagonal
@@ -161,7 +166,7 @@ gp_status gp_nll_batch(const gp_dataset *ds, int32_t batch, const double *theta,
 gp_status gp_nll(const gp_dataset *ds, const double *theta, int32_t prec,
                  void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream);
 
-/* Step a1 alone: write R_delta (eq. 2 plus nugget) for `batch` thetas.
+/* The correlation build alone: write R_delta (eq. 2 plus nugget) for `batch` thetas.
  * R: device, batch matrices of order n_pad = 64*ceil(n/64), column-major with
  * leading dimension ldr (>= n_pad) and batch stride ldr*ldr doubles.  Written:
  * every 64 x 64 tile on or below the diagonal (diagonal tiles in full); the
@@ -170,7 +175,9 @@ gp_status gp_nll(const gp_dataset *ds, const double *theta, int32_t prec,
 gp_status gp_corr_build(const gp_dataset *ds, int32_t batch, const double *theta,
                         double *R, int32_t ldr, int32_t *info, hipStream_t stream);
 
-/* Step a2/a3 alone: in-place blocked Cholesky R = L L' of `batch` symmetric
+/* The factorisation and log-determinant alone (Sec. 2: the determinant and the solves of eq. 3-4 come
+ * from a factorisation of R; Sec. 3: the factorisation is the dominant cost
+ * of an evaluation): in-place blocked Cholesky R = L L' of `batch` symmetric
  * matrices of order n (lower triangle referenced), column-major, leading
  * dimension lda >= 64*ceil(n/64), batch stride lda*lda doubles.  Rows and
  * columns n..n_pad-1 are overwritten with the identity.  On return the lower
@@ -229,7 +236,8 @@ gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
  * (without the factorisation lookahead), and the per-dataset batches run
  * side by side on a pool of eight library-owned streams (default priority,
  * created on first use per device and caller stream and kept for the life
- * of the process) that fork from and join back into `stream`; the paper
+ * of the process; for at most 32 caller streams, further ones run the
+ * batches one after another on `stream`) that fork from and join back into `stream`; the paper
  * evaluated one theta at a time (Sec. 3).  Each result is bitwise the one
  * gp_nll_batch gives for that dataset and theta.  ds, counts: host arrays;
  * counts[k] = 0 skips dataset k (its descriptor is then not read).  ws: at
@@ -258,7 +266,8 @@ gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
  * gp_server_submit: queues host requests (copied).  GP_EWORKSPACE if a
  *   request could never fit the arena.
  * gp_server_poll: non-blocking; retires finished micro-batches into `out`
- *   (at most max_out completions; a batch is reported whole or not at all)
+ *   (at most max_out completions; a batch is reported whole or not at all,
+ *   so max_out is 0 (admit only) or at least max_batch, else GP_EINVAL)
  *   and launches queued work while a stream and arena space are free: the
  *   oldest request picks the dataset, up to max_batch queued requests of it
  *   (arrival order) form the batch, shrunk until it fits.  Returns the number

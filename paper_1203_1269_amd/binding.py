@@ -52,6 +52,13 @@ def header_constant(name: str) -> int:
     return int(m.group(1))
 
 
+def header_constant_expr(name: str) -> int:
+    """A header constant written as a number or as (a << b), with an optional
+    u suffix."""
+    m = re.search(rf"#define\s+{name}\s+\(?\s*(\d+)u?\s*(?:<<\s*(\d+))?\s*\)?", open(HEADER).read())
+    return int(m.group(1)) << int(m.group(2) or 0)
+
+
 class GPError(RuntimeError):
     pass
 

@@ -474,7 +474,11 @@ namespace {
 // Side streams (and their events) of one caller stream, created on first use
 // per (device, caller stream) and kept for the life of the process: `s` for
 // the lookahead trailing updates, `solve` for the solve segments.  Default
-// priority, non-blocking.
+// priority, non-blocking.  At most SIDE_CALLERS caller streams get them;
+// calls on further streams factor without the lookahead (same results), so a
+// caller that cycles through new streams does not make the library create
+// streams without bound.
+constexpr size_t SIDE_CALLERS = 64;
 struct SideStream {
     hipStream_t s = nullptr;
     hipEvent_t fork = nullptr, join = nullptr;
@@ -492,6 +496,7 @@ SideStream *side_for(hipStream_t caller)
     auto key = std::make_pair(dev, caller);
     auto it = table.find(key);
     if (it != table.end()) return it->second.s ? &it->second : nullptr;
+    if (table.size() >= SIDE_CALLERS) return nullptr;
     SideStream sd;
     if (hipStreamCreateWithFlags(&sd.s, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) != hipSuccess ||
@@ -529,8 +534,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                   int extra, const SolvePlan *plan)
 {
     const int nparts = np / TB;
-    // the INT8 trailing update is built for one rank (OZ_RANK)
-    const int nb = prec == GP_MIXED ? OZ_RANK : OUTER_NB;
+    const int nb = prec == GP_MIXED ? mixed_rank() : OUTER_NB;
     SideStream *sd = lookahead && (bordered || np > 2 * nb) ? side_for(s) : nullptr;
     bool pending = false;   // the side stream holds an update not yet joined
     for (int c = 0; c < np; c += nb) {
@@ -565,15 +569,20 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             pending = false;
         }
         const int K = pe - c;
-        const bool i8 = prec == GP_MIXED && !bordered && extra == 0 && oz_sl && oz_ex &&
-                        ozaki_handles(np, pe, K);
-        if (i8) launch_ozaki_split(A, lda, bstride, np, pe, c, K, batch, oz_sl, oz_ex, s, mask);
+        const bool mixed = prec == GP_MIXED && !bordered && extra == 0 && oz_sl && oz_ex;
+        const bool digits = mixed && mixed_digits() && ozaki_handles(np, pe, K);
+        const CrtConst *cc = mixed && !digits ? crt_constants(K) : nullptr;
+        if (digits) launch_ozaki_split(A, lda, bstride, np, pe, c, K, batch, oz_sl, oz_ex, s, mask);
+        if (cc) launch_crt_split(A, lda, bstride, np, pe, c, K, batch, *cc, oz_sl, oz_ex, s, mask);
         const int upd_prec = prec == GP_MIXED ? GP_FP64 : prec;
         auto update = [&](int cs, int ce, hipStream_t st) {
             if (ce <= cs) return;
-            if (i8)
+            if (digits)
                 launch_syrk_update_i8(A, lda, bstride, np, pe, cs, ce, K, batch, oz_sl, oz_ex, st,
                                       mask);
+            else if (cc)
+                launch_syrk_update_crt(A, lda, bstride, np, pe, cs, ce, K, batch, *cc, oz_sl, oz_ex,
+                                       st, mask);
             else
                 launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, batch, st, upd_prec, mask);
         };

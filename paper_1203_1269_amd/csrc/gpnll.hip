@@ -4,6 +4,8 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 using namespace gpk;
@@ -53,7 +55,8 @@ bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
         L.oz_ex = off;
         off += align_up(sizeof(int32_t) * (size_t)L.np * batch);
         L.oz_sl = off;
-        off += align_up(ozaki_slices_bytes(L.np, batch));
+        off += align_up(std::max(ozaki_slices_bytes(L.np, batch),
+                                 crt_residue_bytes(L.np, mixed_rank(), batch)));
     }
     if (prec == GP_MIXED_FAST) {
         const size_t vec = align_up(sizeof(double) * 2 * (size_t)L.np * batch);

@@ -104,6 +104,10 @@ __device__ __forceinline__ double corr_dlog(double th, double D)
         else { LAUNCH(0); }                          \
     } while (0)
 
+// Raise the dynamic-LDS limit of kernel `fn` to `bytes` on the current
+// device, once per (device, kernel) for the life of the process.
+void allow_dynamic_lds(const void *fn, int bytes);
+
 // Optional per-theta mask (mask[b] == 0: the launch leaves theta b alone;
 // nullptr: all thetas) used to rerun a subset of a batch on the FP64 path.
 
@@ -111,7 +115,7 @@ __device__ __forceinline__ double corr_dlog(double th, double D)
 void launch_init(const double *theta, int d, int batch, int32_t *info, hipStream_t s,
                  const uint8_t *mask = nullptr);
 
-// a1: R_delta tiles on and below the diagonal, identity padding.
+// Correlation build: R_delta tiles on and below the diagonal, identity padding.
 void launch_corr_build(const double *X, int n, int d, double p, double delta,
                        const double *theta, int batch, double *R, int lda,
                        size_t bstride, int np, hipStream_t s, const uint8_t *mask = nullptr);
@@ -120,7 +124,7 @@ void launch_corr_build(const double *X, int n, int d, double p, double delta,
 void launch_pad_identity(double *A, int lda, size_t bstride, int n, int np, int batch,
                          hipStream_t s);
 
-// a2: factorisation steps.
+// Factorisation steps.
 // lk: batch * 64 * 64 doubles, the current diagonal factor copy for TRSM.
 void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int batch,
                        int32_t *info, double *lpart, int nparts, double *lk, hipStream_t s,
@@ -147,10 +151,10 @@ struct SolvePlan {
     gp_result *out;
 };
 
-// The whole blocked factorisation (a2) plus log-det partials (a3).  With
+// The whole blocked factorisation plus log-det partials.  With
 // `bordered`, A has order 2 np and holds [[R, I], [I, 0]]; only the first np
 // columns are factored, which leaves L^-T bottom-left and -R^-1 bottom-right.
-// With a solve plan the forward solves and eq. 3-4 (a4, a6) are done as well.
+// With a solve plan the forward solves and eq. 3-4 are done as well.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
                   const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
@@ -203,7 +207,41 @@ void launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, i
                            int K, int batch, const int8_t *sl, const int32_t *ex, hipStream_t s,
                            const uint8_t *mask = nullptr);
 
-// a5: iterative refinement of R x = [1 y] with FP64 residuals (R regenerated
+// GP_MIXED trailing update by modular arithmetic on INT8 MFMA (crt.hip):
+// per row of the panel block P (rows pe .. np-1, K columns from kc0) an
+// exponent and the residues of its fixed-point integers modulo CRT_NMOD
+// moduli, then C -= P P^T over the columns [cs, ce) (multiples of 64 from
+// pe) reconstructed from the per-modulus INT8 products.  K is 256, 512, 768
+// or 1024.
+constexpr int CRT_NMOD = 16;
+struct CrtConst {
+    int b;                    // fraction bits of the per-row fixed point
+    int pad_;
+    double Mscaled;           // (m_1 ... m_N) 2^-2b
+    float mf[CRT_NMOD];       // moduli and reciprocals (FP32: reduction of the products)
+    float inv[CRT_NMOD];
+    double md[CRT_NMOD];      // moduli and reciprocals (FP64: residues of the split)
+    double invd[CRT_NMOD];
+    double t29[CRT_NMOD];     // 2^29 mod m_l
+    double f1[CRT_NMOD];      // y_l / m_l = f1 + f2, f1 a multiple of 2^-40
+    double f2[CRT_NMOD];
+};
+bool crt_setup(int K, CrtConst &c);
+// constants for rank K (computed once per K), nullptr if K is not handled
+const CrtConst *crt_constants(int K);
+// outer panel width (= rank of the trailing updates) of GP_MIXED
+int mixed_rank();
+bool mixed_digits();
+// residue bytes for `batch` matrices of order np at rank K (rows padded to 128)
+size_t crt_residue_bytes(int np, int K, int batch);
+void launch_crt_split(const double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
+                      int batch, const CrtConst &cc, int8_t *sl, int32_t *ex, hipStream_t s,
+                      const uint8_t *mask = nullptr);
+void launch_syrk_update_crt(double *A, int lda, size_t bstride, int np, int pe, int cs, int ce,
+                            int K, int batch, const CrtConst &cc, const int8_t *sl,
+                            const int32_t *ex, hipStream_t s, const uint8_t *mask = nullptr);
+
+// Iterative refinement of R x = [1 y] with FP64 residuals (R regenerated
 // from X) and corrections through the factor A; then mu, sigma2, nll.
 // rhs, x, s: batch * 2 np doubles each.
 void refine_solves(const double *A, int lda, size_t bstride, int np, const gp_dataset *ds,
@@ -218,11 +256,11 @@ void launch_adjoint(const double *A, int lda, size_t bstride, int np, int n, int
                     const double *X, const double *theta, const double *alpha,
                     const gp_result *res, double *part, double *grad, int batch, hipStream_t s);
 
-// a3 alone: logdet[b] = sum of the nparts partials.
+// Log-determinant alone: logdet[b] = sum of the nparts partials.
 void launch_logdet_sum(const double *lpart, int nparts, int batch, double *logdet,
                        hipStream_t s);
 
-// a4 + a6: forward solves with [1 y], mu, sigma2, nll; writes gp_result.
+// Forward solves with [1 y], mu, sigma2, nll; writes gp_result.
 // ir_tag goes to gp_result.ir_iters of the thetas written.
 void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n,
                          const double *y, const double *lpart, int nparts,

@@ -23,7 +23,11 @@ constexpr int MULTI_LANES = 8;
 
 // Lanes (streams) plus fork/join events for one caller stream, created on
 // first use per (device, caller stream) and kept for the life of the
-// process.  Default priority, non-blocking.
+// process.  Default priority, non-blocking.  At most MULTI_CALLERS caller
+// streams get lanes; calls on further streams run their groups on the
+// caller's stream, so a caller that cycles through new streams does not make
+// the library create streams without bound.
+constexpr size_t MULTI_CALLERS = 32;
 struct Lanes {
     hipStream_t s[MULTI_LANES] = {};
     hipEvent_t fork = nullptr;
@@ -41,6 +45,7 @@ Lanes *lanes_for(hipStream_t caller)
     auto key = std::make_pair(dev, caller);
     auto it = table.find(key);
     if (it != table.end()) return it->second.ok ? &it->second : nullptr;
+    if (table.size() >= MULTI_CALLERS) return nullptr;
     Lanes L;
     bool ok = hipEventCreateWithFlags(&L.fork, hipEventDisableTiming) == hipSuccess;
     for (int l = 0; ok && l < MULTI_LANES; ++l)

@@ -27,6 +27,8 @@ enum KernelKind {
     K_SYRK_UPDATE_I8,
     K_PRED_ROWS,
     K_PRED_REDUCE,
+    K_CRT_SPLIT,
+    K_SYRK_UPDATE_CRT,
     K_NUM_KINDS
 };
 

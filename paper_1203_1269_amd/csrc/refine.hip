@@ -317,13 +317,7 @@ void launch_residual(const double *X, int n, int d, double p, double delta, cons
 void launch_solve2(const double *A, int lda, size_t bstride, int np, const double *rhs, double *x,
                    int batch, hipStream_t st)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)solve2_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(2 * GP_NMAX * sizeof(double)));
-        attr_set = true;
-    }
+    allow_dynamic_lds((const void *)solve2_kernel, (int)(2 * GP_NMAX * sizeof(double)));
     const double lower = 0.5 * (double)np * (np + 1);
     ProfScope ps(K_SOLVE2, 8.0 * lower * batch, 16.0 * lower * batch, st);
     solve2_kernel<<<batch, RS_THREADS, (size_t)2 * np * sizeof(double), st>>>(A, lda, bstride, np,

@@ -49,6 +49,7 @@ struct gp_server {
         double *h_theta = nullptr;      // pinned staging, max_batch * GP_DMAX
         gp_result *h_out = nullptr;     // pinned results, max_batch
         bool busy = false;
+        bool failed = false;             // the micro-batch's launch failed
         int dataset = -1, B = 0;
         hipGraphExec_t exec = nullptr;   // kept executable graph (graphs on)
         int g_dataset = -1, g_B = 0;     // the launch sequence it holds
@@ -144,13 +145,9 @@ bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_re
     st.bytes = need;
     st.ids.clear();
     for (const gp_request &r : reqs) st.ids.push_back(r.id);
-    if (rc != GP_OK) {
-        // arguments were validated at submit; mark every result as failed
-        for (int q = 0; q < B; ++q) {
-            st.h_out[q].info = -4;
-            st.h_out[q].logdet = st.h_out[q].mu = st.h_out[q].sigma2 = st.h_out[q].nll = NAN;
-        }
-    }
+    // arguments were validated at submit; a failed launch marks the results
+    // at retirement (the copy into h_out queued above still lands first)
+    st.failed = rc != GP_OK;
     return true;
 }
 
@@ -216,6 +213,9 @@ gp_status gp_server_submit(gp_server *sv, const gp_request *reqs, int32_t count)
 int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
 {
     if (!sv || max_out < 0 || (!out && max_out > 0)) return GP_EINVAL;
+    // a micro-batch is reported whole: room for fewer than max_batch could
+    // leave one unretired for ever
+    if (max_out > 0 && max_out < sv->max_batch) return GP_EINVAL;
     int32_t m = 0;
     // 1. retire finished micro-batches
     for (auto &st : sv->streams) {
@@ -228,7 +228,12 @@ int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
             out[m].dataset = st.dataset;
             out[m].batch = st.B;
             out[m].result = st.h_out[k];
-            if (q != hipSuccess) out[m].result.info = -4;
+            if (q != hipSuccess || st.failed) {
+                gp_result &r = out[m].result;
+                r.info = -4;
+                r.logdet = r.mu = r.sigma2 = r.nll = NAN;
+                r.ir_iters = 0;
+            }
             ++m;
         }
         sv->arena.release(st.off, st.bytes);

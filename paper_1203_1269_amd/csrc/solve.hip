@@ -15,6 +15,10 @@
 // the segment that ends at the last block does the reductions.
 #include <math.h>
 
+#include <mutex>
+#include <set>
+#include <utility>
+
 #include "kernels.hpp"
 
 namespace gpk {
@@ -166,14 +170,8 @@ void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n
                          const double *lpart, int nparts, const int32_t *info, int batch,
                          gp_result *out, hipStream_t s, const uint8_t *mask, int ir_tag)
 {
-    static bool attr_set = false;
     const size_t shm = (size_t)2 * np * sizeof(double);
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)solve_reduce_kernel,
-                            hipFuncAttributeMaxDynamicSharedMemorySize,
-                            (int)(2 * GP_NMAX * sizeof(double)));
-        attr_set = true;
-    }
+    allow_dynamic_lds((const void *)solve_reduce_kernel, (int)(2 * GP_NMAX * sizeof(double)));
     const double lower = 0.5 * (double)np * (np + 1);
     ProfScope ps(K_SOLVE_REDUCE, 4.0 * lower * batch, (8.0 * lower + 16.0 * n) * batch, s);
     solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
@@ -187,20 +185,25 @@ void launch_solve_segment(const double *A, int lda, size_t bstride, int np, int 
                           int ib1, hipStream_t s)
 {
     if (ib1 <= ib0) return;
-    static bool attr_set = false;
     const size_t shm = (size_t)2 * np * sizeof(double);
-    if (!attr_set) {
-        (void)hipFuncSetAttribute((const void *)solve_reduce_kernel,
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(2 * GP_NMAX * sizeof(double)));
-        attr_set = true;
-    }
+    allow_dynamic_lds((const void *)solve_reduce_kernel, (int)(2 * GP_NMAX * sizeof(double)));
     // entries of L read: the lower part of columns [64 ib0, 64 ib1)
     const double c0 = 64.0 * ib0, c1 = 64.0 * ib1;
     const double entries = (c1 - c0) * np - 0.5 * (c1 * c1 - c0 * c0) + 0.5 * (c1 - c0);
     ProfScope ps(K_SOLVE_REDUCE, 4.0 * entries * batch, (8.0 * entries + 32.0 * np) * batch, s);
     solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
                                                        info, out, nullptr, 0, z, ib0, ib1);
+}
+
+void allow_dynamic_lds(const void *fn, int bytes)
+{
+    static std::mutex mu;
+    static std::set<std::pair<int, const void *>> done;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(mu);
+    if (done.insert(std::make_pair(dev, fn)).second)
+        (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
 }
 
 }  // namespace gpk

@@ -75,15 +75,15 @@ def test_workspace_sizing(lib):
     assert lib.gp_workspace_bytes(100, 33, 1, 0) == 0     # d > GP_DMAX
     assert lib.gp_workspace_bytes(100, 2, 0, 0) == 0      # empty batch
     assert lib.gp_workspace_bytes(100, 2, 1, 7) == 0      # unknown precision
-    # the matched-accuracy mixed mode adds GP_MIXED_DIGITS digit slices of
-    # GP_MIXED_RANK bytes per padded row, one exponent per row and a fallback
-    # flag per theta
-    S = binding.header_constant("GP_MIXED_DIGITS")
+    # the matched-accuracy mixed mode adds the INT8 residues of the panel
+    # rows (GP_MIXED_MODULI x GP_MIXED_RANK bytes per row, rows padded to a
+    # multiple of 128), one exponent per row and a fallback flag per theta
+    N = binding.header_constant("GP_MIXED_MODULI")
     K = binding.header_constant("GP_MIXED_RANK")
-    assert (S, K) == (8, 768)
+    assert (N, K) == (16, 768)
     mx = binding.workspace_bytes(4096, 8, 128, "mixed")
-    assert mx >= ws + 128 * 4096 * (S * K + 4)
-    assert mx < ws + 128 * 4096 * (S * K + 4) + (1 << 12)
+    assert mx >= ws + 128 * 4096 * (N * K + 4)
+    assert mx < ws + 128 * 4096 * (N * K + 4) + (1 << 12)
     assert binding.workspace_bytes(4096, 8, 128, "mixed_fast") > ws
     bmax = binding.header_constant("GP_BATCH_MAX")
     assert lib.gp_workspace_bytes(100, 2, bmax, 0) > 0

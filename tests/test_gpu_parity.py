@@ -51,7 +51,7 @@ def check_against_oracle(gp, X, y, theta, p, delta, label):
 
 
 # ---------------------------------------------------------------------------
-# a1: correlation build, entrywise
+# Correlation build, entrywise
 
 @pytest.mark.parametrize("n,d,p", [(200, 2, 2.0), (300, 5, 1.95), (130, 3, 1.0), (77, 12, 1.5),
                                    (64, 20, 0.7)])
@@ -88,7 +88,7 @@ def test_corr_build_flags_invalid_theta(gp):
 
 
 # ---------------------------------------------------------------------------
-# a2/a3: blocked Cholesky and log-determinant on oracle-built matrices
+# Blocked Cholesky and log-determinant on oracle-built matrices
 
 @pytest.mark.parametrize("n", [64, 100, 257, 600, 1000])
 def test_cholesky_factor_entrywise(gp, n):
