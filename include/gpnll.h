@@ -307,6 +307,23 @@ int64_t gp_server_outstanding(const gp_server *server);
 size_t gp_server_arena_used(const gp_server *server);
 gp_status gp_server_destroy(gp_server *server);
 
+/* gp_nll_batch for callers that cannot allocate device memory (code under
+ * HIP stream capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same computation and results as gp_nll_batch, with the workspace taken
+ * from a fixed array of GP_NOALLOC_BYTES in the library's device memory
+ * (one copy per GPU, held from the library's load on that GPU until the
+ * process ends) instead of a caller buffer, and without the factorisation
+ * lookahead (no library streams are created).  The call allocates nothing.
+ * Returns GP_EWORKSPACE when gp_workspace_bytes(n, d, batch, prec) exceeds
+ * GP_NOALLOC_BYTES (e.g. n = 1024 fits 8 FP64 thetas), GP_EINVAL for
+ * invalid arguments, GP_ELAUNCH if the array's device address cannot be
+ * obtained.  Every call on a GPU uses that GPU's one array: calls that
+ * overlap on one GPU (other streams or host threads) race, and each call
+ * overwrites the array's previous contents. */
+#define GP_NOALLOC_BYTES (64u << 20)
+gp_status gp_nll_batch_noalloc(const gp_dataset *ds, int32_t batch, const double *theta,
+                               int32_t prec, gp_result *out, hipStream_t stream);
+
 /* Per-launch timing for measurement.  gp_profile_begin(max_launches) makes
  * every later kernel launch of this library record two hipEvents on its own
  * stream, tagged with that launch's algorithmic FP64 FLOPs and HBM bytes
