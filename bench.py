@@ -350,6 +350,25 @@ def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps, kst_steps=1):
     return out
 
 
+INT8_MFMA_PEAK = 5.0e15   # MI355X dense INT8 matrix peak, OP/s
+
+
+def mixed_roofline(kst):
+    """The matched mixed form's dominant kernel (the INT8 trailing update):
+    INT8 operations it issues per launch (16 modular products of 2K
+    operations per updated lower entry) over its event time, against the
+    INT8 MFMA peak; the FP64-equivalent rate beside it."""
+    if not kst or "syrk_update_crt" not in kst:
+        return None
+    sy = kst["syrk_update_crt"]
+    ops = 16.0 * sy["flops"]
+    achieved = ops / (sy["ms"] * 1e-3)
+    return {"bound": "mfma", "kernel": "syrk_update_crt", "achieved": achieved / 1e12,
+            "peak": INT8_MFMA_PEAK / 1e12, "unit": "TOP/s", "frac": achieved / INT8_MFMA_PEAK,
+            "fp64_equivalent_tflops": sy["flops"] / (sy["ms"] * 1e-3) / 1e12,
+            "launches": sy["launches"], "traffic": None}
+
+
 def large_leg(args, dev):
     """n=8192, d=10, p=2, 32 thetas: FP64, matched-accuracy mixed and the FP32
     mode, each against the stored oracle values of this workload."""
@@ -606,6 +625,7 @@ def main():
                      "traffic_unit": "bytes per launch",
                      "measured": f"HIP events around each launch, {ps} instrumented steps after "
                                  "the timed ones"},
+        "roofline_mixed": mixed_roofline(prof.get("mixed")),
         "factorization_frac_of_fp64_peak": factor_flops * evals / FP64_MFMA_PEAK,
         "results_ok": n_ok,
         "kernels": kernels,

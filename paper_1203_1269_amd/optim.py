@@ -28,6 +28,7 @@ class FitResult:
     iterations: np.ndarray     # S, accepted steps
     evaluations: int           # batched gp_nll_grad calls
     history: list = field(default_factory=list)   # best nll after each iteration
+    start_history: np.ndarray = None                 # (iterations + 1) x S, each start's nll
 
 
 def _eval(ds, phi, ws):
@@ -72,6 +73,7 @@ def lbfgs_multistart(ds: "binding.Dataset", theta0, iters: int = 50, m: int = 10
     active = np.isfinite(f) & (np.max(np.abs(g), axis=1) > gtol)
     its = np.zeros(S, dtype=int)
     history = [float(np.min(f))]
+    per_start = [f.copy()]
     for _ in range(iters):
         if not active.any():
             break
@@ -113,4 +115,6 @@ def lbfgs_multistart(ds: "binding.Dataset", theta0, iters: int = 50, m: int = 10
         its += moved
         active = moved & (np.max(np.abs(g), axis=1) > gtol)
         history.append(float(np.min(f)))
-    return FitResult(np.exp(phi), f, np.max(np.abs(g), axis=1), its, nevals, history)
+        per_start.append(f.copy())
+    return FitResult(np.exp(phi), f, np.max(np.abs(g), axis=1), its, nevals, history,
+                     np.array(per_start))

@@ -173,3 +173,30 @@ def test_lbfgs_multistart_descends_and_matches_scipy(gp):
                           options={"maxiter": 200, "gtol": 1e-10, "ftol": 1e-15})
         print("start", s, "gpu", fit.nll[s], "scipy", ref.fun)
         assert fit.nll[s] <= ref.fun + 1e-7 * abs(ref.fun)
+
+
+def test_lbfgs_fullsize_n4096_d6_two_starts(gp):
+    """The n=4096, d=6 gradient workload: two of its starts, 50 L-BFGS
+    iterations in log(theta) on the GPU.  Each start's history descends, the
+    search moves far from the start, and at each final iterate the value is
+    the FP64 oracle's at that theta (the oracle evaluates it independently;
+    bar 1e-10 relative) and the gradient is at most 1e-2 of its first value."""
+    from paper_1203_1269_amd import optim
+    w = inputs.gradient_workload()
+    th0 = w.theta[:2]
+    print("[parity] lbfgs fullsize n=4096 d=6 starts=2", flush=True)
+    ds = gp.Dataset(w.X, w.y, w.p, w.delta)
+    res0, g0 = gp.nll_grad(ds, th0)
+    g0 = g0.cpu().numpy() * th0
+    fit = optim.lbfgs_multistart(ds, th0, iters=50)
+    hist = fit.start_history
+    assert np.all(np.diff(hist, axis=0) <= 1e-12 * np.abs(hist[:-1])), hist
+    assert np.all(hist[-1] < hist[0] - 1.0)
+    r64 = oracle.nll_batch(w.X, w.y, fit.theta, w.p, w.delta, nthreads=2)
+    assert np.all(r64.info == 0)
+    for s in range(2):
+        e = abs(fit.nll[s] - r64.nll[s]) / max(abs(r64.nll[s]), 1.0)
+        print("start", s, "nll", fit.nll[s], "oracle", r64.nll[s], "rel", e,
+              "grad", fit.grad_norm[s], "first grad", np.abs(g0[s]).max(), flush=True)
+        assert e <= 1e-10
+        assert fit.grad_norm[s] <= 1e-2 * np.abs(g0[s]).max()

@@ -71,7 +71,16 @@ def test_corr_build_entrywise(gp, n, d, p):
         ref = oracle.corr(X, th[b], p, delta, extended=True)
         low = np.tril(np.ones((n, n), dtype=bool))
         err = np.abs(G[:n, :n] - ref)[low]
-        assert np.all(err <= 2e-15 * np.maximum(1.0, 0.0) + 1e-13 * np.abs(ref[low])), err.max()
+        # ulp bar from the arithmetic: the exponent s = sum_k theta_k |dx_k|^p
+        # carries at most (d + 4) u s of rounding (pow within 2 ulp, the
+        # product and d - 1 additions of positive terms within half an ulp
+        # each, with slack), and exp(-s) adds 2 ulp; relative to R_ij that
+        # is ((d + 4) s + 2) u, u = 2^-53 (entries below 1e-300: absolute)
+        r = ref[low]
+        s_ = -np.log(np.maximum(r, 1e-300))
+        bar = ((d + 4) * s_ + 2) * 2.0 ** -53 * r + 1e-300
+        assert np.all(err <= bar), (err / np.maximum(bar, 1e-300)).max()
+        print(f"corr n={n} d={d} p={p}: worst error / ulp bar {(err / bar).max():.3f}")
         assert np.all(np.diag(G)[:n] == 1.0 + delta)
         # padding is the identity
         assert np.all(G[n:, :n] == 0.0)
