@@ -332,15 +332,11 @@ def mixed_summary(prec, dt, kst, res, dt64, res64, w, steps, kst_steps=1):
            "matched_1e-8": bool(errs["nll"] is not None and errs["nll"] <= 1e-8 and ok.all()),
            "kernels_ms_per_step": {k: v["ms"] / kst_steps for k, v in kst.items()}}
     if prec == "mixed":
-        # INT8 MFMA operations issued per FP64 product: 16 modular products
-        # (CRT update), or S(S+1)/2 digit pairs (digit update)
+        # INT8 MFMA operations issued per FP64 product: one product per modulus
         from paper_1203_1269_amd import binding
-        if "syrk_update_crt" in kst:
-            sy, per, out["int8_scheme"] = kst["syrk_update_crt"], 16, "crt16"
-        else:
-            S = binding.header_constant("GP_MIXED_DIGITS")
-            sy = kst.get("syrk_update_i8", {"flops": 0.0, "ms": 1.0})
-            per, out["int8_scheme"] = S * (S + 1) // 2, f"digits{S}"
+        per = binding.header_constant("GP_MIXED_MODULI")
+        sy = kst.get("syrk_update_crt", {"flops": 0.0, "ms": 1.0})
+        out["int8_products_per_fp64_product"] = per
         out["trailing_update_fp64_equiv_tflops"] = sy["flops"] / (sy["ms"] * 1e-3) / 1e12
         out["trailing_update_int8_tops"] = per * sy["flops"] / (sy["ms"] * 1e-3) / 1e12
         out["trailing_update_frac_of_int8_peak"] = out["trailing_update_int8_tops"] / 5000.0

@@ -62,7 +62,6 @@ extern "C" {
 #define GP_DMAX 32
 #define GP_BATCH_MAX 65535
 #define GP_MIXED_MODULI 16  /* INT8 moduli of the GP_MIXED trailing update */
-#define GP_MIXED_DIGITS 8   /* digits per panel entry of the digit-split update */
 #define GP_MIXED_RANK 768   /* rank of the GP_MIXED trailing updates (outer panel width) */
 
 typedef enum {

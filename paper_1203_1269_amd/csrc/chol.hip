@@ -5,7 +5,7 @@
 //
 // Two-level blocking:
 //   outer panels of OUTER_NB = 512 columns (GP_MIXED_RANK = 768 for GP_MIXED,
-//   whose INT8 update is built for that rank); each is factored by inner steps of TB = 64
+//   the rank of its INT8 updates); each is factored by inner steps of TB = 64
 //   columns, left-looking inside the panel (update of the 64-column block by
 //   the panel's earlier blocks, POTRF of its 64 x 64 diagonal tile, TRSM of
 //   the rows below it); then the trailing matrix receives one right-looking
@@ -530,11 +530,12 @@ SideStream *side_for(hipStream_t caller)
 // operations in the same order as one whole solve.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
-                  const uint8_t *mask, int8_t *oz_sl, int32_t *oz_ex, bool lookahead,
+                  const uint8_t *mask, int8_t *crt_res, int32_t *crt_ex, bool lookahead,
                   int extra, const SolvePlan *plan)
 {
     const int nparts = np / TB;
-    const int nb = prec == GP_MIXED ? mixed_rank() : OUTER_NB;
+    // GP_MIXED: wider panels, the rank of its INT8 trailing updates
+    const int nb = prec == GP_MIXED ? GP_MIXED_RANK : OUTER_NB;
     SideStream *sd = lookahead && (bordered || np > 2 * nb) ? side_for(s) : nullptr;
     bool pending = false;   // the side stream holds an update not yet joined
     for (int c = 0; c < np; c += nb) {
@@ -569,20 +570,15 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             pending = false;
         }
         const int K = pe - c;
-        const bool mixed = prec == GP_MIXED && !bordered && extra == 0 && oz_sl && oz_ex;
-        const bool digits = mixed && mixed_digits() && ozaki_handles(np, pe, K);
-        const CrtConst *cc = mixed && !digits ? crt_constants(K) : nullptr;
-        if (digits) launch_ozaki_split(A, lda, bstride, np, pe, c, K, batch, oz_sl, oz_ex, s, mask);
-        if (cc) launch_crt_split(A, lda, bstride, np, pe, c, K, batch, *cc, oz_sl, oz_ex, s, mask);
+        const bool mixed = prec == GP_MIXED && !bordered && extra == 0 && crt_res && crt_ex;
+        const CrtConst *cc = mixed ? crt_constants(K) : nullptr;
+        if (cc) launch_crt_split(A, lda, bstride, np, pe, c, K, batch, *cc, crt_res, crt_ex, s, mask);
         const int upd_prec = prec == GP_MIXED ? GP_FP64 : prec;
         auto update = [&](int cs, int ce, hipStream_t st) {
             if (ce <= cs) return;
-            if (digits)
-                launch_syrk_update_i8(A, lda, bstride, np, pe, cs, ce, K, batch, oz_sl, oz_ex, st,
-                                      mask);
-            else if (cc)
-                launch_syrk_update_crt(A, lda, bstride, np, pe, cs, ce, K, batch, *cc, oz_sl, oz_ex,
-                                       st, mask);
+            if (cc)
+                launch_syrk_update_crt(A, lda, bstride, np, pe, cs, ce, K, batch, *cc, crt_res,
+                                       crt_ex, st, mask);
             else
                 launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, batch, st, upd_prec, mask);
         };

@@ -29,7 +29,6 @@
 // 16x16x4 block, one 16x16x64 INT8 MFMA takes 16): a 2.2x MFMA-cycle
 // advantage over FP64 before the reduction work.
 #include <math.h>
-#include <stdlib.h>
 
 #include <mutex>
 
@@ -408,22 +407,6 @@ const CrtConst *crt_constants(int K)
     const int i = K / 256;
     std::call_once(once[i], [&] { ok[i] = crt_setup(K, table[i]); });
     return ok[i] ? &table[i] : nullptr;
-}
-
-int mixed_rank()
-{
-    static int r = [] {
-        const char *e = getenv("GPNLL_MIXED_RANK");
-        const int v = e ? atoi(e) : GP_MIXED_RANK;
-        return (v >= 256 && v <= 1024 && v % 256 == 0) ? v : GP_MIXED_RANK;
-    }();
-    return r;
-}
-
-bool mixed_digits()
-{
-    static bool d = getenv("GPNLL_MIXED_DIGITS") != nullptr;
-    return d;
 }
 
 size_t crt_residue_bytes(int np, int K, int batch) { return crt_theta_bytes(np, K) * batch; }

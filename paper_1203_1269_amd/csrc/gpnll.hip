@@ -4,8 +4,6 @@
 #include <math.h>
 #include <string.h>
 
-#include <algorithm>
-
 #include "kernels.hpp"
 
 using namespace gpk;
@@ -28,7 +26,7 @@ struct Layout {
     size_t z;        // forward-solve state between solve segments, batch * 2 np doubles
     size_t rhs, x, s; // refinement vectors (mixed mode), batch * 2 np doubles each
     size_t mask;     // per-theta FP64 fallback mask (mixed modes), batch bytes
-    size_t oz_sl, oz_ex; // digit slices and row exponents (GP_MIXED)
+    size_t crt_res, crt_ex; // INT8 residues and row exponents (GP_MIXED)
     size_t total;
 };
 
@@ -48,15 +46,14 @@ bool layout_for(int n, int batch, Layout &L, int prec = GP_FP64)
     off = align_up(off + sizeof(double) * TB * TB * (size_t)batch);
     L.z = off;
     off = align_up(off + sizeof(double) * 2 * (size_t)L.np * batch);
-    L.rhs = L.x = L.s = L.mask = L.oz_sl = L.oz_ex = off;
+    L.rhs = L.x = L.s = L.mask = L.crt_res = L.crt_ex = off;
     if (prec == GP_MIXED) {
         L.mask = off;
         off += align_up((size_t)batch);
-        L.oz_ex = off;
+        L.crt_ex = off;
         off += align_up(sizeof(int32_t) * (size_t)L.np * batch);
-        L.oz_sl = off;
-        off += align_up(std::max(ozaki_slices_bytes(L.np, batch),
-                                 crt_residue_bytes(L.np, mixed_rank(), batch)));
+        L.crt_res = off;
+        off += align_up(crt_residue_bytes(L.np, GP_MIXED_RANK, batch));
     }
     if (prec == GP_MIXED_FAST) {
         const size_t vec = align_up(sizeof(double) * 2 * (size_t)L.np * batch);
@@ -164,7 +161,7 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
     // panel (solve segments on their own stream), ending with eq. 3-4
     SolvePlan plan{ds->y, ds->n, (double *)(base + L.z), out};
     factor_batch(A, np, L.bstride, np, batch, info, lpart, lk, stream, prec, false, nullptr,
-                 (int8_t *)(base + L.oz_sl), (int32_t *)(base + L.oz_ex), lookahead, 0,
+                 (int8_t *)(base + L.crt_res), (int32_t *)(base + L.crt_ex), lookahead, 0,
                  prec == GP_MIXED_FAST ? nullptr : &plan);
     if (prec == GP_FP64) return launched();
     if (prec == GP_MIXED_FAST)

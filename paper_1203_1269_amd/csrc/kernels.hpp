@@ -157,8 +157,8 @@ struct SolvePlan {
 // With a solve plan the forward solves and eq. 3-4 are done as well.
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
-                  const uint8_t *mask = nullptr, int8_t *oz_sl = nullptr,
-                  int32_t *oz_ex = nullptr, bool lookahead = true, int extra = 0,
+                  const uint8_t *mask = nullptr, int8_t *crt_res = nullptr,
+                  int32_t *crt_ex = nullptr, bool lookahead = true, int extra = 0,
                   const SolvePlan *plan = nullptr);
 
 // Predictions: rows np .. np + extra - 1 below the n_pad x n_pad matrix ride
@@ -188,25 +188,6 @@ gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *thet
                          void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream,
                          bool lookahead);
 
-// GP_MIXED trailing update: digits of the panel rows pe .. np-1 (OZ_S slices)
-// and one exponent per row, then the INT8-MFMA product over the columns
-// [cs, ce) (multiples of 64 from pe).  ozaki_handles() tells whether the
-// shape is the rank-OZ_RANK one these kernels take.
-#ifndef OZ_S
-#define OZ_S GP_MIXED_DIGITS
-#endif
-#ifndef OZ_RANK
-#define OZ_RANK GP_MIXED_RANK   // rank of the INT8 trailing update = GP_MIXED panel width
-#endif
-size_t ozaki_slices_bytes(int np, int batch);
-bool ozaki_handles(int np, int pe, int K);
-void launch_ozaki_split(const double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,
-                        int batch, int8_t *sl, int32_t *ex, hipStream_t s,
-                        const uint8_t *mask = nullptr);
-void launch_syrk_update_i8(double *A, int lda, size_t bstride, int np, int pe, int cs, int ce,
-                           int K, int batch, const int8_t *sl, const int32_t *ex, hipStream_t s,
-                           const uint8_t *mask = nullptr);
-
 // GP_MIXED trailing update by modular arithmetic on INT8 MFMA (crt.hip):
 // per row of the panel block P (rows pe .. np-1, K columns from kc0) an
 // exponent and the residues of its fixed-point integers modulo CRT_NMOD
@@ -229,9 +210,6 @@ struct CrtConst {
 bool crt_setup(int K, CrtConst &c);
 // constants for rank K (computed once per K), nullptr if K is not handled
 const CrtConst *crt_constants(int K);
-// outer panel width (= rank of the trailing updates) of GP_MIXED
-int mixed_rank();
-bool mixed_digits();
 // residue bytes for `batch` matrices of order np at rank K (rows padded to 128)
 size_t crt_residue_bytes(int np, int K, int batch);
 void launch_crt_split(const double *A, int lda, size_t bstride, int np, int pe, int kc0, int K,

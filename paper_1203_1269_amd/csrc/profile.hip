@@ -12,7 +12,7 @@ namespace gpk {
 const char *const kKindNames[K_NUM_KINDS] = {
     "init", "corr_build", "potrf_diag", "trsm_panel", "syrk_update", "syrk_panel",
     "syrk_update_f32", "solve_reduce", "pad_identity", "logdet_sum", "border_init", "alpha", "adjoint", "residual", "solve2",
-    "ozaki_split", "syrk_update_i8", "pred_rows", "pred_reduce", "crt_split", "syrk_update_crt"};
+    "pred_rows", "pred_reduce", "crt_split", "syrk_update_crt"};
 
 namespace {
 

@@ -23,8 +23,6 @@ enum KernelKind {
     K_ADJOINT,
     K_RESIDUAL,
     K_SOLVE2,
-    K_OZAKI_SPLIT,
-    K_SYRK_UPDATE_I8,
     K_PRED_ROWS,
     K_PRED_REDUCE,
     K_CRT_SPLIT,
