@@ -24,6 +24,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+# The request-server leg keeps up to 8 micro-batches in flight on as many
+# streams (plus the library's side streams); HIP maps a process's streams
+# onto 4 hardware queues unless told otherwise, which serialises the excess.
+# Set before the HIP runtime starts (first device call).
+os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+
 METRIC = "-2logL evals/sec at n=4096,d=8 (mixed vs FP64 GPU); p50/p99 request latency"
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
 HBM_PEAK = 8.0e12          # MI355X HBM3E, bytes/s
@@ -199,47 +205,44 @@ def multi_leg(args, dev, per=16):
 
 def serving_leg(args, dev):
     """64 resident datasets (n uniform over multiples of 64 in [256, 6144],
-    d in 2..12, p in {1.5, 1.95, 2}); a closed-loop burst measures the
-    saturation throughput, then Poisson streams at 0.5x and 0.9x of it are
-    replayed open-loop with per-request latency."""
+    d in 2..12, p in {1.5, 1.95, 2}); for each form of micro-batch a
+    closed-loop burst measures the saturation throughput, then Poisson
+    streams at 0.5x and 0.9x of it are replayed open-loop with per-request
+    latency.  Forms: ragged (the oldest requests of any datasets in one
+    ragged launch sequence), one dataset per micro-batch, and the latter
+    launched as captured graphs (burst and 0.5x only)."""
     import numpy as np
     from paper_1203_1269_amd import binding, inputs, serving
     sets = inputs.serving_datasets()
     ds = [binding.Dataset(s.X, s.y, s.p, s.delta, device=dev) for s in sets]
     arena = int(args.serving_arena_gb * (1 << 30))
-    srv = serving.Server(ds, arena_bytes=arena, max_batch=16, nstreams=8)
     N = args.serving_requests
     burst = inputs.serving_requests(sets, count=min(N, 1000), rate=1e9, seed=7)
-    lat, _, bsz, wall = serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
-                                       [r[1] for r in burst])
-    sat = len(burst) / wall
-    out = {"datasets": len(ds), "arena_gb": args.serving_arena_gb, "max_batch": 16, "streams": 8,
-           "saturation_evals_per_s": sat}
-    for frac in (0.5, 0.9):
-        reqs = inputs.serving_requests(sets, count=N, rate=frac * sat, seed=8)
-        lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
-                                             [r[1] for r in reqs])
-        summ = serving.latency_summary(lat, wall)
-        summ["offered_rate"] = frac * sat
-        summ["mean_batch"] = float(np.mean(bsz))
-        summ["failed"] = int(sum(1 for r in res if r["info"] != 0))
-        out[f"poisson_{frac}"] = summ
-    srv.close()
-    # the same burst and the 0.5x stream with every micro-batch launched as a
-    # captured graph
-    srv = serving.Server(ds, arena_bytes=arena, max_batch=16, nstreams=8, graphs=True)
-    lat, _, bsz, wall = serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
-                                       [r[1] for r in burst])
-    g = {"saturation_evals_per_s": len(burst) / wall}
-    reqs = inputs.serving_requests(sets, count=N, rate=0.5 * sat, seed=8)
-    lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
-                                         [r[1] for r in reqs])
-    summ = serving.latency_summary(lat, wall)
-    summ["offered_rate"] = 0.5 * sat
-    summ["failed"] = int(sum(1 for r in res if r["info"] != 0))
-    g["poisson_0.5"] = summ
-    out["graphs"] = g
-    srv.close()
+
+    def run(fracs, **cfg):
+        srv = serving.Server(ds, arena_bytes=arena, **cfg)
+        lat, _, bsz, wall = serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
+                                           [r[1] for r in burst])
+        sat = len(burst) / wall
+        out = dict(cfg)
+        out["saturation_evals_per_s"] = sat
+        for frac in fracs:
+            reqs = inputs.serving_requests(sets, count=N, rate=frac * sat, seed=8)
+            lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                                 [r[1] for r in reqs])
+            summ = serving.latency_summary(lat, wall)
+            summ["offered_rate"] = frac * sat
+            summ["mean_batch"] = float(np.mean(bsz))
+            summ["failed"] = int(sum(1 for r in res if r["info"] != 0))
+            out[f"poisson_{frac}"] = summ
+        srv.close()
+        return out
+
+    out = {"datasets": len(ds), "arena_gb": args.serving_arena_gb,
+           "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}
+    out["ragged"] = run((0.5, 0.9), max_batch=64, nstreams=4, ragged=True)
+    out["by_dataset"] = run((0.5, 0.9), max_batch=16, nstreams=8)
+    out["by_dataset_graphs"] = run((0.5,), max_batch=16, nstreams=8, graphs=True)
     return out
 
 
@@ -659,6 +662,14 @@ def main():
         "n8192_mixed_vs_fp64": (line.get("large_n8192") or {}).get("mixed", {}).get(
             "speedup_vs_fp64"),
     }
+    sv = line.get("serving")
+    if sv:
+        for form in ("ragged", "by_dataset"):
+            f = sv[form]
+            line["summary"][f"serving_{form}"] = {
+                "saturation_evals_per_s": f["saturation_evals_per_s"],
+                "p50_ms_at_0.9": f["poisson_0.9"]["p50_ms"],
+                "p99_ms_at_0.9": f["poisson_0.9"]["p99_ms"]}
     print(json.dumps(line), flush=True)
 
 

@@ -231,18 +231,29 @@ gp_status gp_predict(const gp_dataset *ds, int32_t batch, const double *theta,
  * (k < nds; any n, d and correlation family per dataset), the thetas of
  * dataset k stored as a counts[k] x d_k row-major block, blocks concatenated
  * in dataset order in `theta` (device); results in the same order in `out`
- * (device, sum of counts).  Each dataset's thetas run as one gp_nll_batch
- * (without the factorisation lookahead), and the per-dataset batches run
- * side by side on a pool of eight library-owned streams (default priority,
- * created on first use per device and caller stream and kept for the life
- * of the process; for at most 32 caller streams, further ones run the
- * batches one after another on `stream`) that fork from and join back into `stream`; the paper
- * evaluated one theta at a time (Sec. 3).  Each result is bitwise the one
- * gp_nll_batch gives for that dataset and theta.  ds, counts: host arrays;
- * counts[k] = 0 skips dataset k (its descriptor is then not read).  ws: at
- * least gp_multi_workspace_bytes(ds, nds, counts, prec) bytes, 256-byte
- * aligned (one gp_nll_batch workspace per dataset with work).  Returns
- * GP_EINVAL for an invalid descriptor or count before anything is launched. */
+ * (device, sum of counts).  The paper evaluated one theta at a time and
+ * names concurrent evaluations as the parallelism it could not use (Sec. 3).
+ *   GP_FP64: one ragged batch.  Each theta's matrix has its own order
+ *     (n_pad of its dataset); the correlation build runs per dataset, then
+ *     one launch sequence factors and solves all matrices together (each
+ *     launch covers the matrices that still have columns at that step), so
+ *     the panel steps of every theta advance in the same kernels.  The sum
+ *     of counts is at most GP_BATCH_MAX.
+ *   GP_MIXED, GP_MIXED_FAST: each dataset's thetas run as one gp_nll_batch
+ *     (without the factorisation lookahead), the per-dataset batches side by
+ *     side on a pool of eight library-owned streams (default priority,
+ *     created on first use per device and caller stream and kept for the
+ *     life of the process; for at most 32 caller streams, further ones run
+ *     the batches one after another on `stream`) that fork from and join
+ *     back into `stream`.
+ * Either way each result is bitwise the one gp_nll_batch gives for that
+ * dataset and theta.  ds, counts: host arrays; counts[k] = 0 skips dataset k
+ * (its descriptor is then not read).  ws: at least
+ * gp_multi_workspace_bytes(ds, nds, counts, prec) bytes, 256-byte aligned
+ * (FP64: the matrices at their own orders plus per-theta vectors at the
+ * largest; mixed: one gp_nll_batch workspace per dataset with work).
+ * Returns GP_EINVAL for an invalid descriptor or count before anything is
+ * launched. */
 size_t gp_multi_workspace_bytes(const gp_dataset *ds, int32_t nds, const int32_t *counts,
                                 int32_t prec);
 gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
@@ -269,7 +280,9 @@ gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
  *   so max_out is 0 (admit only) or at least max_batch, else GP_EINVAL)
  *   and launches queued work while a stream and arena space are free: the
  *   oldest request picks the dataset, up to max_batch queued requests of it
- *   (arrival order) form the batch, shrunk until it fits.  Returns the number
+ *   (arrival order) form the batch, shrunk until it fits; with `ragged`, the
+ *   oldest max_batch requests of any datasets form the batch (shrunk from
+ *   the newest until it fits) and run as one ragged FP64 batch.  Returns the number
  *   of completions written or a negative gp_status.  A result of a batch whose
  *   launch failed has info = -4.
  * gp_server_outstanding: requests queued or on the GPU.
@@ -296,6 +309,11 @@ typedef struct {
                                 graph (kept per stream and updated in place
                                 for the same dataset and batch size); 0: direct
                                 kernel launches */
+    int32_t ragged;          /* 1 (GP_FP64, graphs 0): a micro-batch is the
+                                oldest max_batch queued requests of any
+                                datasets, run as one ragged batch (the
+                                FP64 path of gp_nll_multi); 0: one dataset per
+                                micro-batch */
 } gp_server_config;
 
 gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *arena,

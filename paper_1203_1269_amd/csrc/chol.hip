@@ -57,25 +57,74 @@ __device__ __forceinline__ double quad_bcast(double v, int q)
 // (double-buffered, one barrier).  Division by the pivot is a multiplication
 // by its reciprocal.  Also writes 2 sum_j ln L_jj of the tile (wave-level
 // reduction) and the first failing pivot (1-based, global) into info.
+// With K > 0 the tile first receives its update by the K columns [kc0, c0)
+// of the same outer panel (left-looking inside the panel): C - P P^T for the
+// tile's rows P of those columns, on FP64 MFMA (wave w: columns 16w..16w+15,
+// the 16x16x4 operand layouts of the trailing update below, D[i][j] in lane
+// j + 16 (i % 4), element i / 4), staged through LDS.  The accumulators
+// start at -C and gather +P P^T: on a diagonal the products shrink the
+// running sum towards the small pivot, so each rounding is relative to that
+// shrinking sum (summing P P^T from zero and subtracting it from C at the
+// end measured 3-4x larger errors on ill-conditioned matrices).
 
 constexpr int PO_THREADS = 256;
 
 __global__ __launch_bounds__(PO_THREADS)
-void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
-                       int32_t *__restrict__ info, double *__restrict__ lpart, int nparts,
-                       double *__restrict__ lk0, const uint8_t *__restrict__ mask)
+void potrf_diag_kernel(double *__restrict__ A0, int lda0, size_t bstride, int c0, int kc0,
+                       int K, int32_t *__restrict__ info, double *__restrict__ lpart,
+                       int nparts, double *__restrict__ lk0, const uint8_t *__restrict__ mask,
+                       const RagMat *__restrict__ rag)
 {
     if (mask && !mask[blockIdx.x]) return;   // uniform over the workgroup
     __shared__ double col[2][TB];
     __shared__ double dg[TB];
+    __shared__ double ub[TB][TB + 1];   // U of the in-panel update (K > 0)
     const int b = blockIdx.x;
     const int tid = threadIdx.x;
     const int q = tid & 3, r = tid >> 2;
-    double *A = A0 + (size_t)b * bstride + (size_t)c0 + (size_t)c0 * lda;
+    int lda = lda0;
+    size_t boff = (size_t)b * bstride;
+    if (rag) {   // ragged batch: this matrix may end before column block c0
+        if (c0 >= rag[b].live) return;
+        lda = rag[b].lda;
+        boff = rag[b].off;
+    }
+    double *A = A0 + boff + (size_t)c0 + (size_t)c0 * lda;
+
+    if (K > 0) {   // uniform
+        const int wave = tid >> 6, lane = tid & 63, li = lane & 15, g = lane >> 4;
+        const double *P = A0 + boff + (size_t)c0 + (size_t)(kc0 + g) * lda;
+        dbl4 u[4];
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            const double *pc = A + (size_t)(16 * rb + g) + (size_t)(16 * wave + li) * lda;
+            u[rb] = -(dbl4){pc[0], pc[4], pc[8], pc[12]};
+        }
+#pragma unroll 4
+        for (int k = 0; k < K; k += 4) {
+            const double *pk = P + (size_t)k * lda;
+            const double fb = pk[16 * wave + li];
+            double fa[4];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb) fa[rb] = pk[16 * rb + li];
+#pragma unroll
+            for (int rb = 0; rb < 4; ++rb)
+                u[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[rb], fb, u[rb], 0, 0, 0);
+        }
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+            ub[16 * rb + g][16 * wave + li] = -u[rb].x;
+            ub[16 * rb + 4 + g][16 * wave + li] = -u[rb].y;
+            ub[16 * rb + 8 + g][16 * wave + li] = -u[rb].z;
+            ub[16 * rb + 12 + g][16 * wave + li] = -u[rb].w;
+        }
+        __syncthreads();
+    }
 
     double a[16];
 #pragma unroll
-    for (int m = 0; m < 16; ++m) a[m] = A[(size_t)r + (size_t)(q + 4 * m) * lda];
+    for (int m = 0; m < 16; ++m)
+        a[m] = K > 0 ? ub[r][q + 4 * m] : A[(size_t)r + (size_t)(q + 4 * m) * lda];
 
     int first_bad = 0;
 #pragma unroll
@@ -120,51 +169,158 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda, size_t bstride, int c0,
 }
 
 // ---------------------------------------------------------------------------
-// TRSM: rows below the diagonal tile, X L_kk' = A, i.e. per row
-// x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj, right-looking over j.  One lane
-// per row with its 64 entries in registers.  The workgroup copies L_kk (the
-// copy written by potrf_diag, diagonal holding 1 / L_jj) into LDS once; every
-// lane of a wave then needs the same L value at the same time, an LDS
-// broadcast.  (Scalar loads of L straight from memory, each wave fetching
-// the 32 KiB itself, measured 0.8% slower overall, bitwise the same.)
+// Rows below the diagonal tile, fused: the in-panel update of the 64-column
+// block (left-looking, by the K columns [kc0, c0) of the same outer panel)
+// and then the TRSM X L_kk' = A, i.e. per row
+// x_j = (a_j - sum_{m<j} x_m L_jm) / L_jj.
+// One wave per 16 PT_RB rows, the block held as X^T in 4 x PT_RB
+// accumulator tiles of the 16x16x4 FP64 MFMA: tile (cb, rb) holds X^T rows 16 cb .. (columns of
+// X) by columns 16 rb .. (rows of X), lane li + 16 g, element e being
+// X(row 16 rb + li, column 16 cb + 4 e + g).  In that layout element q of
+// every lane is exactly the B operand (B[k][j] in lane j + 16 k) of k-step q
+// of a product with X^T on the right, so no data moves between lanes for
+// the MFMA parts:
+//   update:  X^T -= P_kk P_rows^T   (A operand: rows of the diagonal tile,
+//            B operand: the wave's rows, both over the panel columns);
+//   TRSM, per 16-column block jb of L_kk: forward substitution inside the
+//            block (column by column; the finished column is broadcast from
+//            the 16 lanes that hold it, L from LDS), then
+//            X^T(cb) -= L(cb, jb) X^T(jb) on MFMA for the later blocks cb.
+// No inverse is formed: the arithmetic is that of a blocked forward
+// substitution.  L_kk is the copy written by potrf_diag (diagonal holding
+// 1 / L_jj), staged in LDS once per workgroup.  Rows come in whole waves
+// (the row limit is a multiple of 64).  PT_RB = 2 (32 rows per wave) keeps
+// the tile and two fragment sets in the 256 registers of two waves per SIMD.
 
-constexpr int TR_THREADS = 256;
-constexpr int TR_ROWS = TR_THREADS;
-#ifndef TR_MIN_BLOCKS
-#define TR_MIN_BLOCKS 2
+#ifndef PT_RB
+#define PT_RB 2
 #endif
+constexpr int TR_THREADS = 256;
+constexpr int TR_ROWS = 4 * 16 * PT_RB;   // 4 waves
 
-__global__ __launch_bounds__(TR_THREADS, TR_MIN_BLOCKS)
-void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int c0,
-                       const double *__restrict__ lk0, const uint8_t *__restrict__ mask)
+__global__ __launch_bounds__(TR_THREADS, 2)
+void panel_trsm_kernel(double *__restrict__ A0, int lda0, size_t bstride, int np, int c0,
+                       int kc0, int K, const double *__restrict__ lk0,
+                       const uint8_t *__restrict__ mask, const RagMat *__restrict__ rag)
 {
     const int b = blockIdx.y;
     if (mask && !mask[b]) return;   // uniform over the workgroup
-    double *A = A0 + (size_t)b * bstride;
-    __shared__ double lk[TB * TB];
-    for (int e = threadIdx.x; e < TB * TB; e += TR_THREADS) lk[e] = lk0[(size_t)b * TB * TB + e];
+    int lda = lda0;
+    size_t boff = (size_t)b * bstride;
+    if (rag) {   // ragged batch: rows of this matrix end at its own order
+        np = min(np, rag[b].live);
+        if (c0 + TB + (int)blockIdx.x * TR_ROWS >= np) return;   // uniform
+        lda = rag[b].lda;
+        boff = rag[b].off;
+    }
+    __shared__ double lks[TB * TB];
+    for (int e = threadIdx.x; e < TB * TB; e += TR_THREADS) lks[e] = lk0[(size_t)b * TB * TB + e];
     __syncthreads();
-    const int row = c0 + TB + blockIdx.x * TR_ROWS + threadIdx.x;
-    if (row >= np) return;   // after the only barrier
-    double x[TB];
-    {
-        const double *p = A + (size_t)row + (size_t)c0 * lda;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
+    constexpr int RB = PT_RB;
+    const int r0 = c0 + TB + blockIdx.x * TR_ROWS + 16 * RB * wave;
+    if (r0 >= np) return;   // whole waves; after the only barrier
+    double *A = A0 + boff;
+
+    // -X_pre^T = -C^T + P_kk P_rows^T
+    dbl4 T[4][RB];
 #pragma unroll
-        for (int c = 0; c < TB; ++c) { x[c] = *p; p += lda; }
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const double *p = A + (size_t)(r0 + 16 * rb + li) + (size_t)(c0 + 16 * cb + g) * lda;
+            const size_t s4 = (size_t)4 * lda;
+            T[cb][rb] = -(dbl4){p[0], p[s4], p[2 * s4], p[3 * s4]};
+        }
+    if (K > 0) {
+        const double *pd = A + (size_t)(c0 + li) + (size_t)(kc0 + g) * lda;
+        const double *pr = A + (size_t)(r0 + li) + (size_t)(kc0 + g) * lda;
+        const size_t step4 = (size_t)4 * lda;
+        // two fragment sets in flight, as in the trailing update; the reloads
+        // past the end re-read the last k-step (in bounds, unused)
+        double fa[2][4], fb[2][RB];
+#pragma unroll
+        for (int st = 0; st < 2; ++st) {
+#pragma unroll
+            for (int q = 0; q < 4; ++q) fa[st][q] = pd[st * step4 + 16 * q];
+#pragma unroll
+            for (int q = 0; q < RB; ++q) fb[st][q] = pr[st * step4 + 16 * q];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int k = 0; k < K; k += 8) {
+#pragma unroll
+            for (int st = 0; st < 2; ++st) {
+#pragma unroll
+                for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+                    for (int rb = 0; rb < RB; ++rb)
+                        T[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[st][cb], fb[st][rb],
+                                                                         T[cb][rb], 0, 0, 0);
+                const size_t nx = (k + 4 * (2 + st) < K) ? (size_t)(2 + st) * step4
+                                                         : (size_t)st * step4;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) fa[st][q] = pd[nx + 16 * q];
+#pragma unroll
+                for (int q = 0; q < RB; ++q) fb[st][q] = pr[nx + 16 * q];
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            pd += 2 * step4;
+            pr += 2 * step4;
+        }
     }
 #pragma unroll
-    for (int j = 0; j < TB; ++j) {
-        x[j] = x[j] * lk[j * TB + j];
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-        for (int c = j + 1; c < TB; ++c) x[c] = fma(-x[j], lk[j * TB + c], x[c]);
+        for (int rb = 0; rb < RB; ++rb) T[cb][rb] = -T[cb][rb];
+
+#pragma unroll
+    for (int jb = 0; jb < 4; ++jb) {
+        // substitution inside column block jb
+#pragma unroll
+        for (int cp = 0; cp < 16; ++cp) {
+            const int e0 = cp >> 2, g0 = cp & 3, c = 16 * jb + cp;
+            const double linv = lks[c * TB + c];
+            double lm[4];   // L(16 jb + 4 e + g, c) for this lane's elements
+#pragma unroll
+            for (int e = 0; e < 4; ++e) lm[e] = lks[c * TB + 16 * jb + 4 * e + g];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                double v = T[jb][rb][e0];
+                v = (g == g0) ? v * linv : v;
+                T[jb][rb][e0] = v;
+                const double xc = __shfl(v, li + 16 * g0, 64);
+#pragma unroll
+                for (int e = 0; e < 4; ++e)
+                    if (4 * e + 3 > cp)   // some lane of element e is right of c
+                        T[jb][rb][e] = (4 * e + g > cp) ? fma(-xc, lm[e], T[jb][rb][e])
+                                                        : T[jb][rb][e];
+            }
+        }
+        // the later column blocks: X^T(cb) -= L(cb, jb) X^T(jb)
+#pragma unroll
+        for (int cb = jb + 1; cb < 4; ++cb)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const double la = -lks[(16 * jb + 4 * q + g) * TB + 16 * cb + li];
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+                    T[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(la, T[jb][rb][q], T[cb][rb],
+                                                                     0, 0, 0);
+            }
     }
-    // recompute the store addresses rather than keeping 64 of them live, so
-    // that two waves fit per SIMD
-    int r2 = row;
-    asm volatile("" : "+v"(r2));
-    double *q = A + (size_t)r2 + (size_t)c0 * lda;
+
 #pragma unroll
-    for (int c = 0; c < TB; ++c) { *q = x[c]; q += lda; }
+    for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            double *p = A + (size_t)(r0 + 16 * rb + li) + (size_t)(c0 + 16 * cb + g) * lda;
+            const size_t s4 = (size_t)4 * lda;
+            p[0] = T[cb][rb].x;
+            p[s4] = T[cb][rb].y;
+            p[2 * s4] = T[cb][rb].z;
+            p[3 * s4] = T[cb][rb].w;
+        }
 }
 
 // ---------------------------------------------------------------------------
@@ -185,34 +341,103 @@ void trsm_panel_kernel(double *__restrict__ A0, int lda, size_t bstride, int np,
 // Work items are mapped XCD-major: blocks are dispatched round-robin over the
 // 8 XCDs, so block id b runs on XCD b % 8; consecutive work items (same
 // matrix) are given to the same XCD and share its L2 for the panel reads.
+// Inside a matrix the 128 x 128 tiles go in blocks of SY_SR tile rows x
+// SY_SC tile columns (column-major inside a block): the tiles an XCD runs
+// at one time (32 CUs x 2 workgroups) then read SY_SR + SY_SC panel blocks
+// of 128 rows between them instead of one row block each, so the panel is
+// fetched from HBM about (1/SY_SC + 1/SY_SR) times per tile rather than once.
 
 constexpr int SY_THREADS = 256;
 constexpr int NXCD = 8;
 #ifndef SY_NSETS
 #define SY_NSETS 2   // fragment sets in flight (prefetch distance in k-steps of 4)
 #endif
+#ifndef SY_SR
+#define SY_SR 8
+#endif
+#ifndef SY_SC
+#define SY_SC 8
+#endif
+
+// Tile t (work order) of the lower 128 x 128 tiles (it >= jt) of NR tile
+// rows and NC tile columns, in blocks of SY_SR x SY_SC tiles, column block
+// by column block, tiles column-major inside a block.
+__device__ __forceinline__ void sy_tile(int t, int NR, int NC, int &it, int &jt)
+{
+    for (int j0 = 0; j0 < NC; j0 += SY_SC) {
+        const int j1 = min(NC, j0 + SY_SC);
+        for (int i0 = j0; i0 < NR; i0 += SY_SR) {
+            const int i1 = min(NR, i0 + SY_SR);
+            int cnt = 0;
+            for (int j = j0; j < j1; ++j) cnt += max(0, i1 - max(i0, j));
+            if (t < cnt) {
+                for (int j = j0; j < j1; ++j) {
+                    const int c = max(0, i1 - max(i0, j));
+                    if (t < c) {
+                        jt = j;
+                        it = max(i0, j) + t;
+                        return;
+                    }
+                    t -= c;
+                }
+            }
+            t -= cnt;
+        }
+    }
+    it = jt = NR;   // not reached for t < the tile count (then out of range)
+}
 
 // WR x WC waves of 64 x 64: <2,2> = 128 x 128 tiles over a lower-triangular
 // column range; <4,1> = 256 x 64 tiles over a single 64-wide column block.
 template <int WR, int WC>
 __global__ __launch_bounds__(SY_THREADS, 2)
-void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np, int cs,
+void syrk_update_kernel(double *__restrict__ A0, int lda0, size_t bstride, int np, int cs,
                         int ce, int kc0, int K, int NR, int ntiles, int batch,
-                        const uint8_t *__restrict__ mask)
+                        const uint8_t *__restrict__ mask, const RagMat *__restrict__ rag)
 {
     constexpr int TR = 64 * WR, TC = 64 * WC;
-    const int W = ntiles * batch;
-    const int per = (W + NXCD - 1) / NXCD;
     const int bid = blockIdx.x;
-    const int work = (bid % NXCD) * per + bid / NXCD;
-    if (work >= W) return;
-    const int b = work / ntiles;
-    if (mask && !mask[b]) return;
-    int t = work - b * ntiles;
+    int b, t, NRb = NR, NCb = WC > 1 ? (ce - cs + TC - 1) / TC : 1;
+    int lda = lda0;
+    size_t boff;
+    if (rag) {
+        // ragged batch: matrix b's own tiles (its order ends at `live`) are
+        // cut into NXCD contiguous pieces, piece x on XCD x, so that every
+        // XCD gets an equal share of every matrix whatever their sizes; the
+        // grid has room for the tiles of the largest (ntiles)
+        const int chunk = (ntiles + NXCD - 1) / NXCD;
+        const int local = bid / NXCD;
+        b = local / chunk;
+        if (b >= batch) return;
+        np = min(np, rag[b].live);
+        NRb = (np - cs + TR - 1) / TR;
+        if (NRb <= 0) return;
+        if (WC > 1) NCb = (min(ce, np) - cs + TC - 1) / TC;
+        const int nt = WC > 1 ? NCb * NRb - NCb * (NCb - 1) / 2 : NRb;
+        const int cb = (nt + NXCD - 1) / NXCD;
+        const int j = local - b * chunk;
+        t = (bid % NXCD) * cb + j;
+        if (j >= cb || t >= nt) return;
+        lda = rag[b].lda;
+        boff = rag[b].off;
+    } else {
+        const int W = ntiles * batch;
+        const int per = (W + NXCD - 1) / NXCD;
+        const int work = (bid % NXCD) * per + bid / NXCD;
+        if (work >= W) return;
+        b = work / ntiles;
+        if (mask && !mask[b]) return;
+        t = work - b * ntiles;
+        boff = (size_t)b * bstride;
+    }
     int jt = 0, it = t;
     if (WC > 1) {
-        while (t >= NR - jt) { t -= NR - jt; ++jt; }
-        it = jt + t;
+        if (SY_SC > 0) {
+            sy_tile(t, NRb, NCb, it, jt);
+        } else {   // column-major over the whole range
+            while (t >= NRb - jt) { t -= NRb - jt; ++jt; }
+            it = jt + t;
+        }
     }
 
     const int wave = threadIdx.x / 64, lane = threadIdx.x % 64;
@@ -220,7 +445,7 @@ void syrk_update_kernel(double *__restrict__ A0, int lda, size_t bstride, int np
     const int c0 = cs + TC * jt + 64 * (wave % WC);
     if (r0 >= np || c0 >= ce || r0 < c0) return;   // no barriers below
 
-    double *A = A0 + (size_t)b * bstride;
+    double *A = A0 + boff;
     const int li = lane & 15, lk = lane >> 4;
     const int pli = 4 * (li & 3) + (li >> 2);   // permuted A row of this lane
 
@@ -415,27 +640,34 @@ __global__ void logdet_sum_kernel(const double *__restrict__ lpart, int nparts, 
 
 }  // namespace
 
-void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int batch, int32_t *info,
-                       double *lpart, int nparts, double *lk, hipStream_t s, const uint8_t *mask)
+// (ragged launches report the figures of the largest matrix for every one)
+void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int kc0, int K, int batch,
+                       int32_t *info, double *lpart, int nparts, double *lk, hipStream_t s,
+                       const uint8_t *mask, const RagMat *rag)
 {
-    ProfScope ps(K_POTRF_DIAG, TB * TB * TB / 3.0 * batch, 16.0 * TB * TB * batch, s);
-    potrf_diag_kernel<<<batch, PO_THREADS, 0, s>>>(A, lda, bstride, c0, info, lpart, nparts, lk,
-                                                   mask);
+    ProfScope ps(K_POTRF_DIAG, (TB * TB * TB / 3.0 + 2.0 * TB * TB * K) * batch,
+                 (16.0 * TB * TB + 8.0 * TB * K) * batch, s);
+    potrf_diag_kernel<<<batch, PO_THREADS, 0, s>>>(A, lda, bstride, c0, kc0, K, info, lpart,
+                                                   nparts, lk, mask, rag);
 }
 
-void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int batch,
-                       const double *lk, hipStream_t s, const uint8_t *mask)
+void launch_panel_trsm(double *A, int lda, size_t bstride, int np, int c0, int kc0, int K,
+                       int batch, const double *lk, hipStream_t s, const uint8_t *mask,
+                       const RagMat *rag)
 {
     int rows = np - (c0 + TB);
     if (rows <= 0) return;
-    ProfScope ps(K_TRSM_PANEL, (double)rows * TB * TB * batch,
-                 (16.0 * rows * TB + 8.0 * TB * TB) * batch, s);
+    // update 2 rows 64 K, substitution rows 64^2; bytes: the block in and
+    // out, the panel rows and L_kk
+    ProfScope ps(K_TRSM_PANEL, ((double)rows * TB * TB + 2.0 * rows * TB * K) * batch,
+                 (16.0 * rows * TB + 8.0 * rows * K + 8.0 * TB * TB) * batch, s);
     dim3 grid((rows + TR_ROWS - 1) / TR_ROWS, batch);
-    trsm_panel_kernel<<<grid, TR_THREADS, 0, s>>>(A, lda, bstride, np, c0, lk, mask);
+    panel_trsm_kernel<<<grid, TR_THREADS, 0, s>>>(A, lda, bstride, np, c0, kc0, K, lk, mask, rag);
 }
 
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce, int kc0,
-                        int K, int batch, hipStream_t s, int prec, const uint8_t *mask)
+                        int K, int batch, hipStream_t s, int prec, const uint8_t *mask,
+                        const RagMat *rag)
 {
     if (ce <= cs || K <= 0) return;
     const double entries = (double)(ce - cs) * np - 0.5 * (double)(cs + ce - 1) * (ce - cs);
@@ -457,16 +689,17 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
         for (int jt = 0; jt < NC; ++jt) ntiles += NR - jt;
     }
     const long W = (long)ntiles * batch;
-    const long per = (W + NXCD - 1) / NXCD;
+    // ragged: NXCD pieces of the largest matrix's tile count per matrix
+    const long per = rag ? (long)((ntiles + NXCD - 1) / NXCD) * batch : (W + NXCD - 1) / NXCD;
     if (block64)
         syrk_update_kernel<4, 1><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask, rag);
     else if (f32)
         syrk_update_f32_kernel<<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
             A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
     else
         syrk_update_kernel<2, 2><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask, rag);
 }
 
 namespace {
@@ -531,9 +764,22 @@ SideStream *side_for(hipStream_t caller)
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered,
                   const uint8_t *mask, int8_t *crt_res, int32_t *crt_ex, bool lookahead,
-                  int extra, const SolvePlan *plan)
+                  int extra, const SolvePlan *plan, const RagMat *rag, const int32_t *hlive)
 {
     const int nparts = np / TB;
+    // ragged batch: the matrices come in order of decreasing order (hlive:
+    // host copy of their `live`), so those a launch at column x still has to
+    // touch (live > x) are the first act(x); the launch covers only them
+    auto act = [&](int x) {
+        if (!hlive) return batch;
+        int lo = 0, hi = batch;
+        while (lo < hi) {
+            const int mid = (lo + hi) / 2;
+            if (hlive[mid] > x) lo = mid + 1;
+            else hi = mid;
+        }
+        return lo;
+    };
     // GP_MIXED: wider panels, the rank of its INT8 trailing updates
     const int nb = prec == GP_MIXED ? GP_MIXED_RANK : OUTER_NB;
     SideStream *sd = lookahead && (bordered || np > 2 * nb) ? side_for(s) : nullptr;
@@ -546,25 +792,30 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
             const int rmax = bordered ? np + c0 + TB : np + extra;
             // left-looking inside the outer panel: bring block c0 up to date
             // with the blocks [c, c0) of the same panel, then factor it
-            if (c0 > c)
-                launch_syrk_update(A, lda, bstride, rmax, c0, c0 + TB, c, c0 - c, batch, s, GP_FP64,
-                                   mask);
-            launch_potrf_diag(A, lda, bstride, c0, batch, info, lpart, nparts, lk, s, mask);
-            launch_trsm_panel(A, lda, bstride, rmax, c0, batch, lk, s, mask);
+            // left-looking inside the outer panel: block c0 is brought up to
+            // date with the blocks [c, c0) of the same panel by the two
+            // kernels that factor it (diagonal tile, then the rows below)
+            const int bc = act(c0), bt = act(c0 + TB);
+            if (bc == 0) break;
+            launch_potrf_diag(A, lda, bstride, c0, c, c0 - c, bc, info, lpart, nparts, lk, s, mask,
+                              rag);
+            if (bt > 0)
+                launch_panel_trsm(A, lda, bstride, rmax, c0, c, c0 - c, bt, lk, s, mask, rag);
         }
         if (plan && sd) {
             // columns [c, pe) of L are final: their part of the forward solve
             (void)hipEventRecord(sd->panel, s);
             (void)hipStreamWaitEvent(sd->solve, sd->panel, 0);
-            launch_solve_segment(A, lda, bstride, np, plan->n, plan->y, lpart, nparts, info, batch,
-                                 plan->out, plan->z, c / TB, pe / TB, sd->solve);
+            launch_solve_segment(A, lda, bstride, np, plan->n, plan->y, lpart, nparts, info, act(c),
+                                 plan->out, plan->z, c / TB, pe / TB, sd->solve, plan->rag);
         }
         // right-looking rank-(pe - c) update of the trailing matrix: rows up
         // to rlim, columns [pe, cend); with a border it also covers the
         // border columns np .. np + pe - 1
         const int rlim = bordered ? np + pe : np + extra;
         const int cend = bordered ? np + pe : np;
-        if (cend <= pe) continue;
+        const int bu = act(pe);
+        if (cend <= pe || bu == 0) continue;
         if (pending) {
             (void)hipStreamWaitEvent(s, sd->join, 0);
             pending = false;
@@ -572,15 +823,16 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
         const int K = pe - c;
         const bool mixed = prec == GP_MIXED && !bordered && extra == 0 && crt_res && crt_ex;
         const CrtConst *cc = mixed ? crt_constants(K) : nullptr;
-        if (cc) launch_crt_split(A, lda, bstride, np, pe, c, K, batch, *cc, crt_res, crt_ex, s, mask);
+        if (cc) launch_crt_split(A, lda, bstride, np, pe, c, K, bu, *cc, crt_res, crt_ex, s, mask);
         const int upd_prec = prec == GP_MIXED ? GP_FP64 : prec;
         auto update = [&](int cs, int ce, hipStream_t st) {
             if (ce <= cs) return;
             if (cc)
-                launch_syrk_update_crt(A, lda, bstride, np, pe, cs, ce, K, batch, *cc, crt_res,
+                launch_syrk_update_crt(A, lda, bstride, np, pe, cs, ce, K, bu, *cc, crt_res,
                                        crt_ex, st, mask);
             else
-                launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, batch, st, upd_prec, mask);
+                launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, bu, st, upd_prec, mask,
+                                   rag);
         };
         const int sp = min(pe + nb, np);   // end of the next panel
         if (sd && cend > sp && sp > pe) {
@@ -599,7 +851,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
         (void)hipStreamWaitEvent(s, sd->solved, 0);
     } else if (plan) {
         launch_solve_segment(A, lda, bstride, np, plan->n, plan->y, lpart, nparts, info, batch,
-                             plan->out, plan->z, 0, np / TB, s);
+                             plan->out, plan->z, 0, np / TB, s, plan->rag);
     }
 }
 

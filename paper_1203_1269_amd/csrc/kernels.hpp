@@ -111,6 +111,23 @@ void allow_dynamic_lds(const void *fn, int bytes);
 // Optional per-theta mask (mask[b] == 0: the launch leaves theta b alone;
 // nullptr: all thetas) used to rerun a subset of a batch on the FP64 path.
 
+// Ragged batches (matrices of different orders in one launch, FP64 path):
+// matrix b starts at A0 + off with leading dimension lda and order `live`
+// (its padded size, a multiple of 64); launches sized for the largest order
+// leave everything of matrix b at or beyond `live` alone.  n and y are the
+// dataset's, for the solves.  With rag == nullptr every matrix is at
+// A0 + b bstride with the launch's lda and order.
+struct RagMat {
+    size_t off;
+    int32_t lda, live;
+    int32_t n, dst;     // dst: index of the matrix's result in `out`
+    const double *y;
+};
+// rag[0 .. count) = src (count <= RAG_CHUNK), a kernel-argument copy so the
+// descriptors need no host buffer that outlives the call
+constexpr int RAG_CHUNK = 32;
+void launch_rag_fill(RagMat *rag, const RagMat *src, int count, hipStream_t s);
+
 // theta validity and info initialisation.
 void launch_init(const double *theta, int d, int batch, int32_t *info, hipStream_t s,
                  const uint8_t *mask = nullptr);
@@ -126,18 +143,22 @@ void launch_pad_identity(double *A, int lda, size_t bstride, int n, int np, int 
 
 // Factorisation steps.
 // lk: batch * 64 * 64 doubles, the current diagonal factor copy for TRSM.
-void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int batch,
+// Block column c0 of an outer panel starting at kc0 (K = c0 - kc0 columns
+// of the panel before it): potrf_diag updates and factors the diagonal tile,
+// panel_trsm updates the rows below (up to np) and solves them against it.
+void launch_potrf_diag(double *A, int lda, size_t bstride, int c0, int kc0, int K, int batch,
                        int32_t *info, double *lpart, int nparts, double *lk, hipStream_t s,
-                       const uint8_t *mask = nullptr);
-void launch_trsm_panel(double *A, int lda, size_t bstride, int np, int c0, int batch,
-                       const double *lk, hipStream_t s, const uint8_t *mask = nullptr);
+                       const uint8_t *mask = nullptr, const RagMat *rag = nullptr);
+void launch_panel_trsm(double *A, int lda, size_t bstride, int np, int c0, int kc0, int K,
+                       int batch, const double *lk, hipStream_t s, const uint8_t *mask = nullptr,
+                       const RagMat *rag = nullptr);
 // C(r, c) -= sum_{k in [kc0, kc0+K)} A(r, k) A(c, k) for c in [cs, ce) and
 // r in [c's 128-tile row .. np), i.e. the lower part of the column range.
 // prec selects the arithmetic of the trailing updates (GP_FP64 or
 // GP_MIXED_FAST); updates of a single 64-column block are always FP64.
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce,
                         int kc0, int K, int batch, hipStream_t s, int prec,
-                        const uint8_t *mask = nullptr);
+                        const uint8_t *mask = nullptr, const RagMat *rag = nullptr);
 
 // Forward solves L [a b] = [1 y] and eq. 3-4 run along with the
 // factorisation: the solve of the columns of each finished outer panel (a
@@ -149,6 +170,7 @@ struct SolvePlan {
     int n;
     double *z;
     gp_result *out;
+    const RagMat *rag = nullptr;   // ragged batch: n and y per matrix
 };
 
 // The whole blocked factorisation plus log-det partials.  With
@@ -159,7 +181,8 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
                   const uint8_t *mask = nullptr, int8_t *crt_res = nullptr,
                   int32_t *crt_ex = nullptr, bool lookahead = true, int extra = 0,
-                  const SolvePlan *plan = nullptr);
+                  const SolvePlan *plan = nullptr, const RagMat *rag = nullptr,
+                  const int32_t *hlive = nullptr);
 
 // Predictions: rows np .. np + extra - 1 below the n_pad x n_pad matrix ride
 // through the factorisation as rows below the diagonal (factor_batch with
@@ -187,6 +210,13 @@ bool dataset_valid(const gp_dataset *ds);
 gp_status nll_batch_impl(const gp_dataset *ds, int32_t batch, const double *theta, int32_t prec,
                          void *ws, size_t ws_bytes, gp_result *out, hipStream_t stream,
                          bool lookahead);
+
+// Ragged FP64 batch over several datasets (multi.hip): counts[k] thetas of
+// dataset k, packed per dataset in order; one launch sequence for all.
+size_t ragged_workspace_bytes(const gp_dataset *ds, int32_t nds, const int32_t *counts);
+gp_status nll_ragged_impl(const gp_dataset *ds, int32_t nds, const int32_t *counts,
+                          const double *theta, void *ws, size_t ws_bytes, gp_result *out,
+                          hipStream_t stream, bool lookahead);
 
 // GP_MIXED trailing update by modular arithmetic on INT8 MFMA (crt.hip):
 // per row of the panel block P (rows pe .. np-1, K columns from kc0) an
@@ -250,7 +280,7 @@ void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n
 void launch_solve_segment(const double *A, int lda, size_t bstride, int np, int n,
                           const double *y, const double *lpart, int nparts,
                           const int32_t *info, int batch, gp_result *out, double *z, int ib0,
-                          int ib1, hipStream_t s);
+                          int ib1, hipStream_t s, const RagMat *rag = nullptr);
 
 // mask[b] = 1 for thetas whose mixed-precision result must be recomputed in
 // FP64 (failed pivot or refinement above the FP64 backward-error level).

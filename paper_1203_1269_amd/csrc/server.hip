@@ -9,7 +9,11 @@
 //      footprint (workspace + theta + results) is carved from the caller's
 //      arena, and the batch is launched on its own stream (theta upload,
 //      gp_nll_batch, result download, event).
-// Micro-batches of different datasets run concurrently on different streams,
+// With `ragged` (FP64), a micro-batch is simply the oldest max_batch queued
+// requests whatever their datasets: they run as one ragged batch
+// (nll_ragged_impl), whose kernels advance every request of the batch
+// together, each matrix at its own order.
+// Micro-batches run concurrently on different streams,
 // so requests that arrive while others are on the GPU start as soon as a
 // stream and memory are free.  Every theta's arithmetic is independent of the
 // rest of its batch and of the other streams, so a request's result is
@@ -26,6 +30,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <algorithm>
 #include <cmath>
 #include <deque>
 #include <vector>
@@ -35,6 +40,13 @@
 
 using namespace gpk;
 
+// Ragged micro-batches factor with the one-panel lookahead (side streams per
+// server stream): the thin tail of a batch's largest matrices then overlaps
+// the next panel.
+#ifndef RAGGED_LOOKAHEAD
+#define RAGGED_LOOKAHEAD true
+#endif
+
 struct gp_server {
     std::vector<gp_dataset> ds;
     char *arena_base = nullptr;
@@ -42,6 +54,7 @@ struct gp_server {
     int max_batch = 32;
     int prec = GP_FP64;
     bool graphs = false;
+    bool ragged = false;
     std::deque<gp_request> pending;
     struct Stream {
         hipStream_t s = nullptr;
@@ -50,11 +63,12 @@ struct gp_server {
         gp_result *h_out = nullptr;     // pinned results, max_batch
         bool busy = false;
         bool failed = false;             // the micro-batch's launch failed
-        int dataset = -1, B = 0;
+        int dataset = -1, B = 0;         // dataset: -1 for a ragged batch
         hipGraphExec_t exec = nullptr;   // kept executable graph (graphs on)
         int g_dataset = -1, g_B = 0;     // the launch sequence it holds
         size_t off = 0, bytes = 0;
         std::vector<int64_t> ids;
+        std::vector<int32_t> dsets;      // dataset of each result (ragged batch)
     };
     std::vector<Stream> streams;
     int64_t in_flight = 0;
@@ -151,6 +165,54 @@ bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_re
     return true;
 }
 
+// Ragged micro-batch of the requests `reqs` (any datasets): they are grouped
+// by dataset (stable) for the launch; results come back in that order.
+bool launch_ragged(gp_server *sv, gp_server::Stream &st, std::vector<gp_request> &reqs)
+{
+    const int nds = (int)sv->ds.size();
+    std::vector<int32_t> counts(nds, 0);
+    for (const gp_request &r : reqs) ++counts[r.dataset];
+    const size_t ws_bytes = ragged_workspace_bytes(sv->ds.data(), nds, counts.data());
+    if (ws_bytes == 0) return false;
+    const int B = (int)reqs.size();
+    std::stable_sort(reqs.begin(), reqs.end(),
+                     [](const gp_request &a, const gp_request &b) { return a.dataset < b.dataset; });
+    size_t nth = 0;
+    for (const gp_request &r : reqs) nth += sv->ds[r.dataset].d;
+    const size_t theta_off = Arena::round(ws_bytes);
+    const size_t out_off = theta_off + Arena::round(sizeof(double) * nth);
+    const size_t need = out_off + Arena::round(sizeof(gp_result) * (size_t)B);
+    size_t off;
+    if (!sv->arena.alloc(need, off)) return false;
+    char *base = sv->arena_base + off;
+    size_t t = 0;
+    for (const gp_request &r : reqs) {
+        const int d = sv->ds[r.dataset].d;
+        memcpy(st.h_theta + t, r.theta, sizeof(double) * d);
+        t += d;
+    }
+    double *d_theta = (double *)(base + theta_off);
+    gp_result *d_out = (gp_result *)(base + out_off);
+    (void)hipMemcpyAsync(d_theta, st.h_theta, sizeof(double) * nth, hipMemcpyHostToDevice, st.s);
+    const gp_status rc = nll_ragged_impl(sv->ds.data(), nds, counts.data(), d_theta, base,
+                                         ws_bytes, d_out, st.s, RAGGED_LOOKAHEAD);
+    (void)hipMemcpyAsync(st.h_out, d_out, sizeof(gp_result) * B, hipMemcpyDeviceToHost, st.s);
+    (void)hipEventRecord(st.done, st.s);
+    st.busy = true;
+    st.dataset = -1;
+    st.B = B;
+    st.off = off;
+    st.bytes = need;
+    st.ids.clear();
+    st.dsets.clear();
+    for (const gp_request &r : reqs) {
+        st.ids.push_back(r.id);
+        st.dsets.push_back(r.dataset);
+    }
+    st.failed = rc != GP_OK;
+    return true;
+}
+
 }  // namespace
 
 extern "C" {
@@ -164,6 +226,8 @@ gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *
     if (cfg->prec != GP_FP64 && cfg->prec != GP_MIXED && cfg->prec != GP_MIXED_FAST)
         return GP_EINVAL;
     if (cfg->graphs != 0 && cfg->graphs != 1) return GP_EINVAL;
+    if (cfg->ragged != 0 && cfg->ragged != 1) return GP_EINVAL;
+    if (cfg->ragged == 1 && (cfg->prec != GP_FP64 || cfg->graphs != 0)) return GP_EINVAL;
     if (((uintptr_t)arena & 255) != 0) return GP_EINVAL;
     for (int k = 0; k < ndatasets; ++k) {
         const gp_dataset &d = datasets[k];
@@ -178,6 +242,7 @@ gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *
     sv->max_batch = cfg->max_batch;
     sv->prec = cfg->prec;
     sv->graphs = cfg->graphs == 1;
+    sv->ragged = cfg->ragged == 1;
     sv->streams.resize(cfg->nstreams);
     for (auto &st : sv->streams) {
         bool ok = hipStreamCreateWithFlags(&st.s, hipStreamNonBlocking) == hipSuccess &&
@@ -225,7 +290,7 @@ int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
         if (q == hipErrorNotReady) continue;
         for (int k = 0; k < st.B; ++k) {
             out[m].id = st.ids[k];
-            out[m].dataset = st.dataset;
+            out[m].dataset = st.dataset >= 0 ? st.dataset : st.dsets[k];
             out[m].batch = st.B;
             out[m].result = st.h_out[k];
             if (q != hipSuccess || st.failed) {
@@ -244,6 +309,22 @@ int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
     for (auto &st : sv->streams) {
         if (st.busy) continue;
         if (sv->pending.empty()) break;
+        if (sv->ragged) {
+            // the oldest max_batch requests, shrunk (newest out) until it fits
+            size_t take = std::min(sv->pending.size(), (size_t)sv->max_batch);
+            bool launched = false;
+            while (take > 0) {
+                std::vector<gp_request> batch(sv->pending.begin(), sv->pending.begin() + (long)take);
+                if (launch_ragged(sv, st, batch)) {
+                    launched = true;
+                    break;
+                }
+                --take;
+            }
+            if (!launched) break;   // the oldest request waits for memory
+            sv->pending.erase(sv->pending.begin(), sv->pending.begin() + (long)take);
+            continue;
+        }
         const int k = sv->pending.front().dataset;
         std::vector<gp_request> batch;
         std::vector<size_t> taken;

@@ -13,6 +13,9 @@
 // runs as soon as those columns of L are final): it then starts from, or
 // leaves, the partial solution in z (2 n_pad doubles per matrix), and only
 // the segment that ends at the last block does the reductions.
+// In a ragged batch each matrix has its own order, n and y (RagMat): the
+// launch covers the blocks of the largest, and a matrix's last block is
+// where its own segment ends and its reductions are done.
 #include <math.h>
 
 #include <mutex>
@@ -40,19 +43,34 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
                          const double *__restrict__ y, const double *__restrict__ lpart,
                          int nparts, const int32_t *__restrict__ info,
                          gp_result *__restrict__ out, const uint8_t *__restrict__ mask,
-                         int ir_tag, double *__restrict__ zg, int ib0, int ib1)
+                         int ir_tag, double *__restrict__ zg, int ib0, int ib1,
+                         const RagMat *__restrict__ rag)
 {
     if (mask && !mask[blockIdx.x]) return;
     extern __shared__ double zs[];          // z0[np], z1[np]
     __shared__ double red[SV_WAVES][3];
+    const int b = blockIdx.x;
+    // the partial solution in zg keeps the launch's stride (2 np per matrix)
+    double *zb = zg ? zg + (size_t)b * 2 * np : nullptr;
+    size_t boff = (size_t)b * bstride;
+    int nlp = nparts;   // log-det partials of this matrix
+    if (rag) {   // uniform over the workgroup
+        const RagMat m = rag[b];
+        if (ib0 * TB >= m.live) return;   // this matrix was finished before
+        np = m.live;
+        lda = m.lda;
+        boff = m.off;
+        n = m.n;
+        y = m.y;
+        nlp = m.live / TB;
+        ib1 = min(ib1, np / TB);
+    }
     double *z0 = zs, *z1 = zs + np;
 
-    const int b = blockIdx.x;
     const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-    const double *A = A0 + (size_t)b * bstride;
+    const double *A = A0 + boff;
     const int T = np / TB;
 
-    double *zb = zg ? zg + (size_t)b * 2 * np : nullptr;
     if (ib0 == 0) {
         // right-hand sides [1 y] (0 in the padded rows)
         for (int r = tid; r < np; r += SV_THREADS) {
@@ -133,7 +151,7 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
     }
     Q = wave_sum(Q);
     double ld = 0.0;
-    for (int q = tid; q < nparts; q += SV_THREADS) ld += lpart[(size_t)b * nparts + q];
+    for (int q = tid; q < nlp; q += SV_THREADS) ld += lpart[(size_t)b * nparts + q];
     ld = wave_sum(ld);
     if (lane == 0) { red[wave][0] = Q; red[wave][2] = ld; }
     __syncthreads();
@@ -160,7 +178,7 @@ void solve_reduce_kernel(const double *__restrict__ A0, int lda, size_t bstride,
             res.nll = ld + (double)n * log(s2);
             res.info = 0;
         }
-        out[b] = res;
+        out[rag ? rag[b].dst : b] = res;
     }
 }
 
@@ -176,13 +194,13 @@ void launch_solve_reduce(const double *A, int lda, size_t bstride, int np, int n
     ProfScope ps(K_SOLVE_REDUCE, 4.0 * lower * batch, (8.0 * lower + 16.0 * n) * batch, s);
     solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
                                                        info, out, mask, ir_tag, nullptr, 0,
-                                                       np / TB);
+                                                       np / TB, nullptr);
 }
 
 void launch_solve_segment(const double *A, int lda, size_t bstride, int np, int n,
                           const double *y, const double *lpart, int nparts,
                           const int32_t *info, int batch, gp_result *out, double *z, int ib0,
-                          int ib1, hipStream_t s)
+                          int ib1, hipStream_t s, const RagMat *rag)
 {
     if (ib1 <= ib0) return;
     const size_t shm = (size_t)2 * np * sizeof(double);
@@ -192,7 +210,8 @@ void launch_solve_segment(const double *A, int lda, size_t bstride, int np, int 
     const double entries = (c1 - c0) * np - 0.5 * (c1 * c1 - c0 * c0) + 0.5 * (c1 - c0);
     ProfScope ps(K_SOLVE_REDUCE, 4.0 * entries * batch, (8.0 * entries + 32.0 * np) * batch, s);
     solve_reduce_kernel<<<batch, SV_THREADS, shm, s>>>(A, lda, bstride, np, n, y, lpart, nparts,
-                                                       info, out, nullptr, 0, z, ib0, ib1);
+                                                       info, out, nullptr, 0, z, ib0, ib1,
+                                                       rag);
 }
 
 void allow_dynamic_lds(const void *fn, int bytes)

@@ -26,7 +26,7 @@ class GPCompletion(ctypes.Structure):
 
 class GPServerConfig(ctypes.Structure):
     _fields_ = [("max_batch", ctypes.c_int32), ("nstreams", ctypes.c_int32),
-                ("prec", ctypes.c_int32), ("graphs", ctypes.c_int32)]
+                ("prec", ctypes.c_int32), ("graphs", ctypes.c_int32), ("ragged", ctypes.c_int32)]
 
 
 _bound = False
@@ -58,15 +58,18 @@ def _bind():
 class Server:
     """Resident datasets + a device arena (admission by HBM footprint) +
     `nstreams` concurrent micro-batches of at most `max_batch` thetas;
-    `graphs` launches each micro-batch as a captured HIP graph."""
+    `graphs` launches each micro-batch as a captured HIP graph; `ragged`
+    (FP64) forms each micro-batch from the oldest requests of any datasets
+    and runs it as one ragged batch."""
 
     def __init__(self, datasets, arena_bytes: int, max_batch: int = 16, nstreams: int = 8,
-                 prec: str = "fp64", device="cuda", graphs: bool = False):
+                 prec: str = "fp64", device="cuda", graphs: bool = False, ragged: bool = False):
         L = _bind()
         self.datasets = list(datasets)
         self.arena = torch.empty(arena_bytes, dtype=torch.uint8, device=device)
         arr = (binding.GPDataset * len(self.datasets))(*[d._c for d in self.datasets])
-        cfg = GPServerConfig(max_batch, nstreams, binding.PRECISIONS[prec], int(bool(graphs)))
+        cfg = GPServerConfig(max_batch, nstreams, binding.PRECISIONS[prec], int(bool(graphs)),
+                             int(bool(ragged)))
         h = ctypes.c_void_p()
         binding._check(L.gp_server_create(arr, len(self.datasets),
                                           ctypes.c_void_p(self.arena.data_ptr()), arena_bytes,

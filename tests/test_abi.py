@@ -166,10 +166,19 @@ def test_multi_dataset_call_checked_on_host(lib):
     arr = (binding.GPDataset * 3)(_ds(n=100, d=2), _ds(n=700, d=5), _ds(n=2, d=2, p=0.0))
     counts = (ctypes.c_int32 * 3)(4, 7, 0)
     need = lib.gp_multi_workspace_bytes(arr, 3, counts, 0)
-    a = lib.gp_workspace_bytes(100, 2, 4, 0)
-    b = lib.gp_workspace_bytes(700, 5, 7, 0)
     up = lambda x: (x + 255) // 256 * 256
-    assert need == up(a) + up(b)     # dataset 2 has no work: its descriptor is not read
+    # FP64: one ragged batch of B = 11 matrices (orders 128 and 704): 32-byte
+    # descriptors, the matrices back to back (per dataset, 256-byte aligned),
+    # then per matrix at the largest order: log-det partials, info, the
+    # 64 x 64 TRSM copy and the 2-vector solve state
+    B, npmax = 11, 704
+    ragged = (up(32 * B) + up(8 * (up(4 * 128 * 128 * 8) // 8 + 7 * 704 * 704)) +
+              up(8 * (npmax // 64) * B) + up(4 * B) + up(8 * 64 * 64 * B) + up(16 * npmax * B))
+    assert need == ragged            # dataset 2 has no work: its descriptor is not read
+    # the mixed modes: one gp_nll_batch workspace per dataset with work
+    a = lib.gp_workspace_bytes(100, 2, 4, 1)
+    b = lib.gp_workspace_bytes(700, 5, 7, 1)
+    assert lib.gp_multi_workspace_bytes(arr, 3, counts, 1) == up(a) + up(b)
     assert lib.gp_multi_workspace_bytes(arr, 3, (ctypes.c_int32 * 3)(4, -1, 0), 0) == 0
     assert lib.gp_multi_workspace_bytes(arr, 3, counts, 9) == 0
     assert lib.gp_multi_workspace_bytes(arr, 3, (ctypes.c_int32 * 3)(0, 0, 0), 0) == 256

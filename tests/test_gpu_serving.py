@@ -1,8 +1,10 @@
 """The continuous-batching request server on the GPU: every request completes
-exactly once, each result is bitwise the one the request gets alone, work of
-different datasets overlaps (several micro-batches in flight), admission
-respects the arena (HBM footprint) and a tiny arena queues instead of
-failing."""
+exactly once, each result is bitwise the one the request gets alone and
+within the FP64 bar of the 80-bit oracle, work of different datasets
+overlaps (several micro-batches in flight), admission respects the arena
+(HBM footprint) and a tiny arena queues instead of failing.  Both forms of
+micro-batch: one dataset each, and ragged (the oldest requests of any
+datasets in one launch sequence)."""
 import numpy as np
 import pytest
 
@@ -27,10 +29,12 @@ def alone(binding, ds, k, th):
     return {key: v.cpu().numpy()[0] for key, v in r.items()}
 
 
-def test_server_results_match_alone(env):
+@pytest.mark.parametrize("ragged", [False, True])
+def test_server_results_match_alone(env, ragged):
     binding, serving, sets, ds = env
     reqs = inputs.serving_requests(sets, count=300, rate=1e6, seed=41)
-    srv = serving.Server(ds, arena_bytes=2 << 30, max_batch=8, nstreams=6)
+    print(f"[serving] alone-vs-served ragged={ragged}", flush=True)
+    srv = serving.Server(ds, arena_bytes=2 << 30, max_batch=8, nstreams=6, ragged=ragged)
     lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
                                          [r[1] for r in reqs], time_limit=120)
     assert srv.outstanding() == 0 and srv.arena_used() == 0
@@ -42,15 +46,52 @@ def test_server_results_match_alone(env):
         for key in ("logdet", "mu", "sigma2", "nll"):
             assert res[q][key] == a[key], (q, key)
         assert res[q]["info"] == a["info"] == 0
+    if ragged:   # micro-batches mixed datasets
+        assert len({reqs[q][1] for q in range(8)}) > 1
     print(serving.latency_summary(lat, wall))
 
 
-def test_server_tiny_arena_queues(env):
+@pytest.mark.parametrize("ragged", [False, True])
+def test_server_results_match_oracle(env, ragged):
+    """Served results (uneven n, d and p across the datasets, requests batched
+    and overlapped on several streams) against the 80-bit oracle: a sample of
+    requests per dataset, every output within max(1e-10, 10 x the FP64
+    rounding spread of two independent FP64 codes) for that theta."""
+    import oracle
+    from parity_util import compare, lapack_fp64, tolerances
+    binding, serving, sets, ds = env
+    reqs = inputs.serving_requests(sets, count=160, rate=1e6, seed=45)
+    print(f"[serving] served-vs-oracle ragged={ragged}", flush=True)
+    srv = serving.Server(ds, arena_bytes=2 << 30, max_batch=8, nstreams=6, ragged=ragged)
+    lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                         [r[1] for r in reqs], time_limit=120)
+    srv.close()
+    assert bsz.max() > 1
+    checked = 0
+    for k, s in enumerate(sets):
+        qs = [q for q in range(len(reqs)) if reqs[q][1] == k][:3]
+        if not qs:
+            continue
+        th = np.array([reqs[q][2] for q in qs])
+        got = {key: np.array([res[q][key] for q in qs]) for key in
+               ("logdet", "mu", "sigma2", "nll", "info")}
+        print(f"[serving] dataset {k}: n={s.X.shape[0]} d={s.X.shape[1]} p={s.p}, {len(qs)} requests",
+              flush=True)
+        r64 = oracle.nll_batch(s.X, s.y, th, s.p, s.delta)
+        r80 = oracle.nll_batch(s.X, s.y, th, s.p, s.delta, extended=True)
+        tol = tolerances(r64, r80, s.y, lapack_fp64(s.X, s.y, th, s.p, s.delta))
+        compare(got, r80, tol, s.y, f"served dataset {k}")
+        checked += len(qs)
+    assert checked >= 16
+
+
+@pytest.mark.parametrize("ragged", [False, True])
+def test_server_tiny_arena_queues(env, ragged):
     binding, serving, sets, ds = env
     # room for about one largest single request at a time
     need = max(binding.workspace_bytes(d.n, d.d, 1) for d in ds) + (1 << 20)
     reqs = inputs.serving_requests(sets, count=40, rate=1e6, seed=42)
-    srv = serving.Server(ds, arena_bytes=need, max_batch=4, nstreams=4)
+    srv = serving.Server(ds, arena_bytes=need, max_batch=4, nstreams=4, ragged=ragged)
     lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
                                          [r[1] for r in reqs], time_limit=120)
     assert all(r is not None and r["info"] == 0 for r in res)
@@ -64,6 +105,10 @@ def test_server_rejects_impossible_request(env):
     with pytest.raises(binding.GPError):
         srv.submit([(0, 0, np.ones(ds[0].d))])
     srv.close()
+    # ragged micro-batches are FP64 only and take no graphs
+    for kw in ({"prec": "mixed"}, {"graphs": True}):
+        with pytest.raises(binding.GPError):
+            serving.Server(ds, arena_bytes=1 << 24, max_batch=4, nstreams=2, ragged=True, **kw)
 
 
 def test_server_mixed_matches_alone(env):
