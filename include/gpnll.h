@@ -280,9 +280,11 @@ gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
  *   so max_out is 0 (admit only) or at least max_batch, else GP_EINVAL)
  *   and launches queued work while a stream and arena space are free: the
  *   oldest request picks the dataset, up to max_batch queued requests of it
- *   (arrival order) form the batch, shrunk until it fits; with `ragged`, the
- *   oldest max_batch requests of any datasets form the batch (shrunk from
- *   the newest until it fits) and run as one ragged FP64 batch.  Returns the number
+ *   (arrival order) form the batch, shrunk until it fits; with `ragged`, up
+ *   to max_batch queued requests of at most 8 datasets, taken in arrival
+ *   order with the oldest request's dataset first (several requests of one
+ *   dataset share the correlation build's power terms), form the batch
+ *   (shrunk from the newest until it fits) and run as one ragged FP64 batch.  Returns the number
  *   of completions written or a negative gp_status.  A result of a batch whose
  *   launch failed has info = -4.
  * gp_server_outstanding: requests queued or on the GPU.
@@ -309,11 +311,10 @@ typedef struct {
                                 graph (kept per stream and updated in place
                                 for the same dataset and batch size); 0: direct
                                 kernel launches */
-    int32_t ragged;          /* 1 (GP_FP64, graphs 0): a micro-batch is the
-                                oldest max_batch queued requests of any
-                                datasets, run as one ragged batch (the
-                                FP64 path of gp_nll_multi); 0: one dataset per
-                                micro-batch */
+    int32_t ragged;          /* 1 (GP_FP64, graphs 0): a micro-batch holds
+                                requests of up to 8 datasets, run as one
+                                ragged batch (the FP64 path of gp_nll_multi);
+                                0: one dataset per micro-batch */
 } gp_server_config;
 
 gp_status gp_server_create(const gp_dataset *datasets, int32_t ndatasets, void *arena,

@@ -393,7 +393,8 @@ template <int WR, int WC>
 __global__ __launch_bounds__(SY_THREADS, 2)
 void syrk_update_kernel(double *__restrict__ A0, int lda0, size_t bstride, int np, int cs,
                         int ce, int kc0, int K, int NR, int ntiles, int batch,
-                        const uint8_t *__restrict__ mask, const RagMat *__restrict__ rag)
+                        const uint8_t *__restrict__ mask, const RagMat *__restrict__ rag,
+                        int whole)
 {
     constexpr int TR = 64 * WR, TC = 64 * WC;
     const int bid = blockIdx.x;
@@ -401,23 +402,37 @@ void syrk_update_kernel(double *__restrict__ A0, int lda0, size_t bstride, int n
     int lda = lda0;
     size_t boff;
     if (rag) {
-        // ragged batch: matrix b's own tiles (its order ends at `live`) are
-        // cut into NXCD contiguous pieces, piece x on XCD x, so that every
-        // XCD gets an equal share of every matrix whatever their sizes; the
-        // grid has room for the tiles of the largest (ntiles)
-        const int chunk = (ntiles + NXCD - 1) / NXCD;
-        const int local = bid / NXCD;
-        b = local / chunk;
+        // ragged batch (matrices in order of decreasing order; the grid has
+        // room for the tiles of the largest, ntiles, per matrix):
+        // `whole`: matrix b on XCD b % NXCD, whole, so that each XCD's L2
+        //   serves one matrix's panel at a time (the host chooses it when
+        //   that spreads the tiles evenly over the XCDs);
+        // else: matrix b's own tiles cut into NXCD contiguous pieces, piece
+        //   x on XCD x, so no XCD idles whatever the sizes.
+        const int x = bid % NXCD, local = bid / NXCD;
+        int j;
+        if (whole) {
+            b = x + NXCD * (local / ntiles);
+            j = local % ntiles;
+        } else {
+            const int chunk = (ntiles + NXCD - 1) / NXCD;
+            b = local / chunk;
+            j = local - b * chunk;
+        }
         if (b >= batch) return;
         np = min(np, rag[b].live);
         NRb = (np - cs + TR - 1) / TR;
         if (NRb <= 0) return;
         if (WC > 1) NCb = (min(ce, np) - cs + TC - 1) / TC;
         const int nt = WC > 1 ? NCb * NRb - NCb * (NCb - 1) / 2 : NRb;
-        const int cb = (nt + NXCD - 1) / NXCD;
-        const int j = local - b * chunk;
-        t = (bid % NXCD) * cb + j;
-        if (j >= cb || t >= nt) return;
+        if (whole) {
+            t = j;
+            if (t >= nt) return;
+        } else {
+            const int cb = (nt + NXCD - 1) / NXCD;
+            t = x * cb + j;
+            if (j >= cb || t >= nt) return;
+        }
         lda = rag[b].lda;
         boff = rag[b].off;
     } else {
@@ -667,7 +682,7 @@ void launch_panel_trsm(double *A, int lda, size_t bstride, int np, int c0, int k
 
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce, int kc0,
                         int K, int batch, hipStream_t s, int prec, const uint8_t *mask,
-                        const RagMat *rag)
+                        const RagMat *rag, const int32_t *hlive)
 {
     if (ce <= cs || K <= 0) return;
     const double entries = (double)(ce - cs) * np - 0.5 * (double)(cs + ce - 1) * (ce - cs);
@@ -689,17 +704,40 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
         for (int jt = 0; jt < NC; ++jt) ntiles += NR - jt;
     }
     const long W = (long)ntiles * batch;
-    // ragged: NXCD pieces of the largest matrix's tile count per matrix
-    const long per = rag ? (long)((ntiles + NXCD - 1) / NXCD) * batch : (W + NXCD - 1) / NXCD;
+    // ragged: whole matrices round-robin over the XCDs when that loads every
+    // XCD within 10% of the mean (from the host copy of the orders), else
+    // NXCD pieces of the largest matrix's tile count per matrix
+    long per = (W + NXCD - 1) / NXCD;
+    int whole = 0;
+    if (rag) {
+        if (hlive && batch >= NXCD) {
+            const int TR = block64 ? 256 : 128, TC = block64 ? 64 : 128;
+            long load[NXCD] = {}, tot = 0;
+            for (int b = 0; b < batch; ++b) {
+                const int nb_ = min(np, (int)hlive[b]);
+                const int nr = (nb_ - cs + TR - 1) / TR;
+                if (nr <= 0) continue;
+                const int nc = block64 ? 1 : (min(ce, nb_) - cs + TC - 1) / TC;
+                const long nt = block64 ? nr : (long)nc * nr - (long)nc * (nc - 1) / 2;
+                load[b % NXCD] += nt;
+                tot += nt;
+            }
+            long mx = 0;
+            for (int x = 0; x < NXCD; ++x) mx = max(mx, load[x]);
+            whole = mx * NXCD <= tot + tot / 10;
+        }
+        per = whole ? (long)ntiles * ((batch + NXCD - 1) / NXCD)
+                    : (long)((ntiles + NXCD - 1) / NXCD) * batch;
+    }
     if (block64)
         syrk_update_kernel<4, 1><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask, rag);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask, rag, whole);
     else if (f32)
         syrk_update_f32_kernel<<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
             A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask);
     else
         syrk_update_kernel<2, 2><<<(unsigned)(per * NXCD), SY_THREADS, 0, s>>>(
-            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask, rag);
+            A, lda, bstride, np, cs, ce, kc0, K, NR, ntiles, batch, mask, rag, whole);
 }
 
 namespace {
@@ -832,7 +870,7 @@ void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t
                                        crt_ex, st, mask);
             else
                 launch_syrk_update(A, lda, bstride, rlim, cs, ce, c, K, bu, st, upd_prec, mask,
-                                   rag);
+                                   rag, hlive);
         };
         const int sp = min(pe + nb, np);   // end of the next panel
         if (sd && cend > sp && sp > pe) {

@@ -158,7 +158,8 @@ void launch_panel_trsm(double *A, int lda, size_t bstride, int np, int c0, int k
 // GP_MIXED_FAST); updates of a single 64-column block are always FP64.
 void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int ce,
                         int kc0, int K, int batch, hipStream_t s, int prec,
-                        const uint8_t *mask = nullptr, const RagMat *rag = nullptr);
+                        const uint8_t *mask = nullptr, const RagMat *rag = nullptr,
+                        const int32_t *hlive = nullptr);
 
 // Forward solves L [a b] = [1 y] and eq. 3-4 run along with the
 // factorisation: the solve of the columns of each finished outer panel (a

@@ -9,10 +9,17 @@
 //      footprint (workspace + theta + results) is carved from the caller's
 //      arena, and the batch is launched on its own stream (theta upload,
 //      gp_nll_batch, result download, event).
-// With `ragged` (FP64), a micro-batch is simply the oldest max_batch queued
-// requests whatever their datasets: they run as one ragged batch
-// (nll_ragged_impl), whose kernels advance every request of the batch
-// together, each matrix at its own order.
+// With `ragged` (FP64), a micro-batch mixes datasets and runs as one ragged
+// batch (nll_ragged_impl), whose kernels advance every request of the batch
+// together, each matrix at its own order.  It is filled in arrival order
+// from the queue with requests of at most RAGGED_DATASETS datasets, the
+// oldest request's first: when the queue is long this gathers several
+// requests per dataset, whose correlation builds then share the |x_i - x_j|^p
+// terms (one request per dataset shares nothing, and the build's pow() is
+// then a large part of the work); when it is short the batch is just the
+// oldest requests.  A request is overtaken only by requests of datasets
+// already in the batch of an older request, at most max_batch - 1 of them
+// per micro-batch.
 // Micro-batches run concurrently on different streams,
 // so requests that arrive while others are on the GPU start as soon as a
 // stream and memory are free.  Every theta's arithmetic is independent of the
@@ -43,9 +50,8 @@ using namespace gpk;
 // Ragged micro-batches factor with the one-panel lookahead (side streams per
 // server stream): the thin tail of a batch's largest matrices then overlaps
 // the next panel.
-#ifndef RAGGED_LOOKAHEAD
-#define RAGGED_LOOKAHEAD true
-#endif
+constexpr bool RAGGED_LOOKAHEAD = true;
+constexpr int RAGGED_DATASETS = 8;
 
 struct gp_server {
     std::vector<gp_dataset> ds;
@@ -310,19 +316,40 @@ int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
         if (st.busy) continue;
         if (sv->pending.empty()) break;
         if (sv->ragged) {
-            // the oldest max_batch requests, shrunk (newest out) until it fits
-            size_t take = std::min(sv->pending.size(), (size_t)sv->max_batch);
+            // in arrival order, requests of at most RAGGED_DATASETS datasets
+            // (the oldest request's first), up to max_batch
+            std::vector<int> chosen;
+            std::vector<size_t> taken;
+            for (size_t q = 0; q < sv->pending.size() && (int)taken.size() < sv->max_batch; ++q) {
+                const int k = sv->pending[q].dataset;
+                if (std::find(chosen.begin(), chosen.end(), k) == chosen.end()) {
+                    if ((int)chosen.size() == RAGGED_DATASETS) continue;
+                    chosen.push_back(k);
+                }
+                taken.push_back(q);
+            }
+            // shrunk (newest out) until its footprint fits
             bool launched = false;
-            while (take > 0) {
-                std::vector<gp_request> batch(sv->pending.begin(), sv->pending.begin() + (long)take);
+            while (!taken.empty()) {
+                std::vector<gp_request> batch;
+                for (size_t q : taken) batch.push_back(sv->pending[q]);
                 if (launch_ragged(sv, st, batch)) {
                     launched = true;
                     break;
                 }
-                --take;
+                taken.pop_back();
             }
             if (!launched) break;   // the oldest request waits for memory
-            sv->pending.erase(sv->pending.begin(), sv->pending.begin() + (long)take);
+            std::deque<gp_request> rest;
+            size_t ti = 0;
+            for (size_t q = 0; q < sv->pending.size(); ++q) {
+                if (ti < taken.size() && taken[ti] == q) {
+                    ++ti;
+                    continue;
+                }
+                rest.push_back(sv->pending[q]);
+            }
+            sv->pending.swap(rest);
             continue;
         }
         const int k = sv->pending.front().dataset;
