@@ -26,9 +26,15 @@ if ROOT not in sys.path:
 
 # The request-server leg keeps up to 8 micro-batches in flight on as many
 # streams (plus the library's side streams); HIP maps a process's streams
-# onto 4 hardware queues unless told otherwise, which serialises the excess.
-# Set before the HIP runtime starts (first device call).
-os.environ.setdefault("GPU_MAX_HW_QUEUES", "8")
+# onto 4 hardware queues unless told otherwise (the usual environment says 4
+# explicitly), which serialises the excess.  At least 8, set before the HIP
+# runtime starts (first device call).
+try:
+    _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
+except ValueError:
+    _hwq = 4
+if _hwq < 8:
+    os.environ["GPU_MAX_HW_QUEUES"] = "8"
 
 METRIC = "-2logL evals/sec at n=4096,d=8 (mixed vs FP64 GPU); p50/p99 request latency"
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
