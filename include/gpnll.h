@@ -207,6 +207,50 @@ gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta,
                       int32_t prec, void *ws, size_t ws_bytes, gp_result *out,
                       double *grad, hipStream_t stream);
 
+/* Batched multi-start L-BFGS on -2logL (the paper fits with a genetic
+ * algorithm and names multi-start gradient methods as the alternative, each
+ * needing many likelihood evaluations, Sec. 2).  `starts` independent
+ * minimisations over phi = log(theta): two-loop recursion over the last m
+ * curvature pairs, backtracking line search (halving, Armijo constant c1,
+ * at most max_ls trials per iteration; the first step of a start without
+ * curvature pairs is at most 1 in phi; trial points clipped to
+ * [log theta_lo, log theta_hi]); a pair is kept when s.y > 1e-12 |s| |y|; a
+ * direction that is not a descent direction restarts that start from the
+ * steepest descent.  A start stops when max_k |d(-2logL)/d phi_k| <= gtol,
+ * when its line search fails, or after `iters` iterations.  Every
+ * value+gradient evaluation is one gp_nll_grad call over the starts still
+ * searching (FP64); the search state lives in the workspace and is updated
+ * by kernels on `stream`.
+ * theta: device, starts x d; in: the starts, out: the final iterates.
+ * nll, gnorm (max_k |d(-2logL)/d log theta_k|): device, starts doubles;
+ * iters: device, starts int32 (accepted steps).  trace: device,
+ * (iters + 1) x starts doubles or NULL: row t holds every start's -2logL
+ * after iteration t (rows past summary->iterations are not written).
+ * summary: host, filled on return.  ws: at least
+ * gp_lbfgs_workspace_bytes(n, d, starts, m) bytes, 256-byte aligned.
+ * 1 <= starts <= 1024, 1 <= m <= 32.  Blocking: the call synchronises
+ * `stream` once per line-search trial (it reads how many starts are still
+ * searching) and returns when the fit is done.  GP_EINVAL for invalid
+ * arguments before anything is launched. */
+typedef struct {
+    int32_t iters;       /* outer iterations */
+    int32_t m;           /* curvature pairs kept */
+    int32_t max_ls;      /* line-search trials per iteration */
+    int32_t reserved;    /* must be 0 */
+    double c1;           /* Armijo constant, (0, 1) */
+    double gtol;         /* stop when max |d(-2logL)/d log theta_k| <= gtol */
+    double theta_lo, theta_hi;   /* 0 < theta_lo < theta_hi */
+} gp_lbfgs_config;
+typedef struct {
+    int32_t iterations;  /* outer iterations run */
+    int32_t evaluations; /* gp_nll_grad calls */
+} gp_lbfgs_summary;
+size_t gp_lbfgs_workspace_bytes(int32_t n, int32_t d, int32_t starts, int32_t m);
+gp_status gp_lbfgs(const gp_dataset *ds, int32_t starts, double *theta,
+                   const gp_lbfgs_config *cfg, void *ws, size_t ws_bytes, double *nll,
+                   double *gnorm, int32_t *iters, double *trace, gp_lbfgs_summary *summary,
+                   hipStream_t stream);
+
 /* Predictions at N test points with the model fitted at each of `batch`
  * thetas (the paper obtains them with one R, one Cholesky factorisation and
  * back-solves per test point, Sec. 3, and scores them by the sum of squared

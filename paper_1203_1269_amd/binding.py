@@ -63,6 +63,16 @@ class GPError(RuntimeError):
     pass
 
 
+class GPLbfgsConfig(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("m", ctypes.c_int32), ("max_ls", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("c1", ctypes.c_double), ("gtol", ctypes.c_double),
+                ("theta_lo", ctypes.c_double), ("theta_hi", ctypes.c_double)]
+
+
+class GPLbfgsSummary(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("evaluations", ctypes.c_int32)]
+
+
 _lib = None
 
 
@@ -100,6 +110,11 @@ def lib():
         L.gp_predict.argtypes = [ctypes.POINTER(GPDataset), i32, vp, vp, i32, i32, vp, sz, vp, vp,
                                  vp, vp]
         L.gp_predict.restype = ctypes.c_int
+        L.gp_lbfgs_workspace_bytes.argtypes = [i32, i32, i32, i32]
+        L.gp_lbfgs_workspace_bytes.restype = sz
+        L.gp_lbfgs.argtypes = [ctypes.POINTER(GPDataset), i32, vp, ctypes.POINTER(GPLbfgsConfig),
+                               vp, sz, vp, vp, vp, vp, ctypes.POINTER(GPLbfgsSummary), vp]
+        L.gp_lbfgs.restype = ctypes.c_int
         L.gp_profile_begin.argtypes = [i32]
         L.gp_profile_begin.restype = ctypes.c_int
         L.gp_profile_end.argtypes = [ctypes.POINTER(GPKernelStat), i32]
@@ -330,6 +345,43 @@ def nll_grad(ds: Dataset, theta, ws: torch.Tensor | None = None):
                            ctypes.c_void_p(grad.data_ptr()), _stream_ptr())
     _check(st, "gp_nll_grad")
     return unpack_results(out), grad
+
+
+def lbfgs_workspace_bytes(n: int, d: int, starts: int, m: int) -> int:
+    return int(lib().gp_lbfgs_workspace_bytes(n, d, starts, m))
+
+
+def lbfgs(ds: Dataset, theta0, iters: int = 50, m: int = 10, c1: float = 1e-4,
+          max_ls: int = 20, gtol: float = 1e-6, theta_bounds=(1e-4, 1e4),
+          ws: torch.Tensor | None = None):
+    """Batched multi-start L-BFGS (gp_lbfgs) from the rows of theta0
+    (S x d).  Returns a dict of device tensors theta (S x d), nll, gnorm,
+    iters, trace ((iterations + 1) x S) and the host counts iterations and
+    evaluations."""
+    th = _dev_f64(theta0, ds.device).reshape(-1, ds.d).clone()
+    S = th.shape[0]
+    need = lbfgs_workspace_bytes(ds.n, ds.d, S, m)
+    if need == 0:
+        raise GPError("gp_lbfgs_workspace_bytes rejected the sizes")
+    if ws is None or ws.numel() < need:
+        ws = alloc_workspace(need, ds.device)
+    dev = ds.device
+    nll = torch.empty(S, dtype=torch.float64, device=dev)
+    gnorm = torch.empty(S, dtype=torch.float64, device=dev)
+    its = torch.empty(S, dtype=torch.int32, device=dev)
+    trace = torch.empty((iters + 1, S), dtype=torch.float64, device=dev)
+    cfg = GPLbfgsConfig(iters, m, max_ls, 0, c1, gtol, float(theta_bounds[0]),
+                        float(theta_bounds[1]))
+    summ = GPLbfgsSummary()
+    st = lib().gp_lbfgs(ds.c, S, ctypes.c_void_p(th.data_ptr()), ctypes.byref(cfg),
+                        ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                        ctypes.c_void_p(nll.data_ptr()), ctypes.c_void_p(gnorm.data_ptr()),
+                        ctypes.c_void_p(its.data_ptr()), ctypes.c_void_p(trace.data_ptr()),
+                        ctypes.byref(summ), _stream_ptr())
+    _check(st, "gp_lbfgs")
+    return {"theta": th, "nll": nll, "gnorm": gnorm, "iters": its,
+            "trace": trace[:summ.iterations + 1], "iterations": summ.iterations,
+            "evaluations": summ.evaluations}
 
 
 class ProfileNLL(torch.autograd.Function):

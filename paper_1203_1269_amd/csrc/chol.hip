@@ -68,6 +68,9 @@ __device__ __forceinline__ double quad_bcast(double v, int q)
 // end measured 3-4x larger errors on ill-conditioned matrices).
 
 constexpr int PO_THREADS = 256;
+#ifndef PT_NSETS
+#define PT_NSETS 4   // fragment sets in flight in the in-panel updates
+#endif
 
 __global__ __launch_bounds__(PO_THREADS)
 void potrf_diag_kernel(double *__restrict__ A0, int lda0, size_t bstride, int c0, int kc0,
@@ -100,16 +103,34 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda0, size_t bstride, int c0
             const double *pc = A + (size_t)(16 * rb + g) + (size_t)(16 * wave + li) * lda;
             u[rb] = -(dbl4){pc[0], pc[4], pc[8], pc[12]};
         }
-#pragma unroll 4
-        for (int k = 0; k < K; k += 4) {
-            const double *pk = P + (size_t)k * lda;
-            const double fb = pk[16 * wave + li];
-            double fa[4];
+        // PT_NSETS fragment sets in flight (K is a multiple of 64), each
+        // reloaded right after its MFMAs; reloads past the end re-read the
+        // set just used (in bounds, unused)
+        constexpr int NS = PT_NSETS;
+        const size_t step4 = (size_t)4 * lda;
+        double fa[NS][4], fb[NS];
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb) fa[rb] = pk[16 * rb + li];
+        for (int st = 0; st < NS; ++st) {
 #pragma unroll
-            for (int rb = 0; rb < 4; ++rb)
-                u[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[rb], fb, u[rb], 0, 0, 0);
+            for (int rb = 0; rb < 4; ++rb) fa[st][rb] = P[st * step4 + 16 * rb + li];
+            fb[st] = P[st * step4 + 16 * wave + li];
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        for (int k = 0; k < K; k += 4 * NS) {
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb)
+                    u[rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[st][rb], fb[st], u[rb], 0, 0, 0);
+                const size_t nx = (k + 4 * (NS + st) < K) ? (size_t)(NS + st) * step4
+                                                          : (size_t)st * step4;
+#pragma unroll
+                for (int rb = 0; rb < 4; ++rb) fa[st][rb] = P[nx + 16 * rb + li];
+                fb[st] = P[nx + 16 * wave + li];
+                asm volatile("" ::: "memory");
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            P += NS * step4;
         }
 #pragma unroll
         for (int rb = 0; rb < 4; ++rb) {
@@ -120,6 +141,7 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda0, size_t bstride, int c0
         }
         __syncthreads();
     }
+
 
     double a[16];
 #pragma unroll
@@ -195,6 +217,7 @@ void potrf_diag_kernel(double *__restrict__ A0, int lda0, size_t bstride, int c0
 #ifndef PT_RB
 #define PT_RB 2
 #endif
+
 constexpr int TR_THREADS = 256;
 constexpr int TR_ROWS = 4 * 16 * PT_RB;   // 4 waves
 
@@ -236,28 +259,31 @@ void panel_trsm_kernel(double *__restrict__ A0, int lda0, size_t bstride, int np
         const double *pd = A + (size_t)(c0 + li) + (size_t)(kc0 + g) * lda;
         const double *pr = A + (size_t)(r0 + li) + (size_t)(kc0 + g) * lda;
         const size_t step4 = (size_t)4 * lda;
-        // two fragment sets in flight, as in the trailing update; the reloads
-        // past the end re-read the last k-step (in bounds, unused)
-        double fa[2][4], fb[2][RB];
+        // PT_NSETS fragment sets in flight (prefetch distance PT_NSETS
+        // k-steps; K is a multiple of 64), each reloaded right after its
+        // MFMAs, as in the trailing update; the reloads past the end re-read
+        // the set just used (in bounds, unused)
+        constexpr int NS = PT_NSETS;
+        double fa[NS][4], fb[NS][RB];
 #pragma unroll
-        for (int st = 0; st < 2; ++st) {
+        for (int st = 0; st < NS; ++st) {
 #pragma unroll
             for (int q = 0; q < 4; ++q) fa[st][q] = pd[st * step4 + 16 * q];
 #pragma unroll
             for (int q = 0; q < RB; ++q) fb[st][q] = pr[st * step4 + 16 * q];
             __builtin_amdgcn_sched_barrier(0);
         }
-        for (int k = 0; k < K; k += 8) {
+        for (int k = 0; k < K; k += 4 * NS) {
 #pragma unroll
-            for (int st = 0; st < 2; ++st) {
+            for (int st = 0; st < NS; ++st) {
 #pragma unroll
                 for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
                     for (int rb = 0; rb < RB; ++rb)
                         T[cb][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[st][cb], fb[st][rb],
                                                                          T[cb][rb], 0, 0, 0);
-                const size_t nx = (k + 4 * (2 + st) < K) ? (size_t)(2 + st) * step4
-                                                         : (size_t)st * step4;
+                const size_t nx = (k + 4 * (NS + st) < K) ? (size_t)(NS + st) * step4
+                                                          : (size_t)st * step4;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) fa[st][q] = pd[nx + 16 * q];
 #pragma unroll
@@ -265,8 +291,8 @@ void panel_trsm_kernel(double *__restrict__ A0, int lda0, size_t bstride, int np
                 asm volatile("" ::: "memory");
                 __builtin_amdgcn_sched_barrier(0);
             }
-            pd += 2 * step4;
-            pr += 2 * step4;
+            pd += NS * step4;
+            pr += NS * step4;
         }
     }
 #pragma unroll

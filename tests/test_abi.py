@@ -223,3 +223,42 @@ def test_product_code_never_uses_the_oracle():
         text = open(path, errors="replace").read()
         assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), path
         assert "liboracle" not in text and "gp_oracle" not in text, path
+
+
+def test_lbfgs_call_checked_on_host(lib):
+    """gp_lbfgs rejects bad arguments (and a short workspace) before it
+    launches anything."""
+    from paper_1203_1269_amd import binding
+    vp = ctypes.c_void_p
+    ds = _ds(n=300, d=3)
+    need = lib.gp_lbfgs_workspace_bytes(300, 3, 4, 10)
+    assert need > lib.gp_grad_workspace_bytes(300, 3, 4)
+    assert lib.gp_lbfgs_workspace_bytes(300, 3, 0, 10) == 0        # no starts
+    assert lib.gp_lbfgs_workspace_bytes(300, 3, 1025, 10) == 0     # too many starts
+    assert lib.gp_lbfgs_workspace_bytes(300, 3, 4, 0) == 0         # no history
+    assert lib.gp_lbfgs_workspace_bytes(300, 3, 4, 33) == 0
+    assert lib.gp_lbfgs_workspace_bytes(300, 33, 4, 10) == 0       # d too large
+
+    def call(S=4, cfg=None, ws=1 << 24, wsb=None, summ=True, ds_=ds, **kw):
+        c = binding.GPLbfgsConfig(50, 10, 20, 0, 1e-4, 1e-6, 1e-4, 1e4)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        s = binding.GPLbfgsSummary()
+        return lib.gp_lbfgs(ctypes.byref(ds_), S, vp(1 << 22), ctypes.byref(c), vp(ws),
+                            need if wsb is None else wsb, vp(1 << 23), vp(1 << 23),
+                            vp(1 << 23), None, ctypes.byref(s) if summ else None, None)
+    assert call(wsb=need - 1) == binding.GP_EWORKSPACE
+    assert call(ws=(1 << 24) + 8) == binding.GP_EINVAL              # unaligned workspace
+    assert call(S=0) == binding.GP_EINVAL
+    assert call(m=0) == binding.GP_EINVAL
+    assert call(max_ls=0) == binding.GP_EINVAL
+    assert call(iters=-1) == binding.GP_EINVAL
+    assert call(c1=0.0) == binding.GP_EINVAL
+    assert call(c1=1.0) == binding.GP_EINVAL
+    assert call(gtol=float("nan")) == binding.GP_EINVAL
+    assert call(theta_lo=0.0) == binding.GP_EINVAL
+    assert call(theta_hi=1e-5) == binding.GP_EINVAL                 # below theta_lo
+    assert call(theta_hi=float("inf")) == binding.GP_EINVAL
+    assert call(reserved=1) == binding.GP_EINVAL
+    assert call(summ=False) == binding.GP_EINVAL
+    assert call(ds_=_ds(n=1)) == binding.GP_EINVAL
