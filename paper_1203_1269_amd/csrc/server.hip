@@ -171,6 +171,24 @@ bool launch_batch(gp_server *sv, gp_server::Stream &st, int k, std::vector<gp_re
     return true;
 }
 
+// Footprint of a ragged micro-batch with counts[k] requests of dataset k:
+// workspace, then the packed thetas, then the results.
+size_t ragged_bytes(const gp_server *sv, const std::vector<int32_t> &counts, size_t &ws_bytes,
+                    size_t &theta_off, size_t &out_off)
+{
+    const int nds = (int)sv->ds.size();
+    ws_bytes = ragged_workspace_bytes(sv->ds.data(), nds, counts.data());
+    if (ws_bytes == 0) return 0;
+    size_t nth = 0, B = 0;
+    for (int k = 0; k < nds; ++k) {
+        nth += (size_t)counts[k] * sv->ds[k].d;
+        B += counts[k];
+    }
+    theta_off = Arena::round(ws_bytes);
+    out_off = theta_off + Arena::round(sizeof(double) * nth);
+    return out_off + Arena::round(sizeof(gp_result) * B);
+}
+
 // Ragged micro-batch of the requests `reqs` (any datasets): they are grouped
 // by dataset (stable) for the launch; results come back in that order.
 bool launch_ragged(gp_server *sv, gp_server::Stream &st, std::vector<gp_request> &reqs)
@@ -178,16 +196,14 @@ bool launch_ragged(gp_server *sv, gp_server::Stream &st, std::vector<gp_request>
     const int nds = (int)sv->ds.size();
     std::vector<int32_t> counts(nds, 0);
     for (const gp_request &r : reqs) ++counts[r.dataset];
-    const size_t ws_bytes = ragged_workspace_bytes(sv->ds.data(), nds, counts.data());
-    if (ws_bytes == 0) return false;
+    size_t ws_bytes, theta_off, out_off;
+    const size_t need = ragged_bytes(sv, counts, ws_bytes, theta_off, out_off);
+    if (need == 0) return false;
     const int B = (int)reqs.size();
     std::stable_sort(reqs.begin(), reqs.end(),
                      [](const gp_request &a, const gp_request &b) { return a.dataset < b.dataset; });
     size_t nth = 0;
     for (const gp_request &r : reqs) nth += sv->ds[r.dataset].d;
-    const size_t theta_off = Arena::round(ws_bytes);
-    const size_t out_off = theta_off + Arena::round(sizeof(double) * nth);
-    const size_t need = out_off + Arena::round(sizeof(gp_result) * (size_t)B);
     size_t off;
     if (!sv->arena.alloc(need, off)) return false;
     char *base = sv->arena_base + off;
@@ -272,9 +288,15 @@ gp_status gp_server_submit(gp_server *sv, const gp_request *reqs, int32_t count)
     for (int q = 0; q < count; ++q) {
         const gp_request &r = reqs[q];
         if (r.dataset < 0 || r.dataset >= (int)sv->ds.size()) return GP_EINVAL;
-        size_t a, b, c;
-        if (batch_bytes(sv->ds[r.dataset], 1, sv->prec, a, b, c) > sv->arena.size())
-            return GP_EWORKSPACE;   // would never fit
+        size_t a, b, c, one;
+        if (sv->ragged) {
+            std::vector<int32_t> counts(sv->ds.size(), 0);
+            counts[r.dataset] = 1;
+            one = ragged_bytes(sv, counts, a, b, c);
+        } else {
+            one = batch_bytes(sv->ds[r.dataset], 1, sv->prec, a, b, c);
+        }
+        if (one > sv->arena.size()) return GP_EWORKSPACE;   // would never fit
     }
     for (int q = 0; q < count; ++q) sv->pending.push_back(reqs[q]);
     sv->in_flight += count;

@@ -262,3 +262,27 @@ def test_lbfgs_call_checked_on_host(lib):
     assert call(reserved=1) == binding.GP_EINVAL
     assert call(summ=False) == binding.GP_EINVAL
     assert call(ds_=_ds(n=1)) == binding.GP_EINVAL
+
+
+def test_server_config_checked_on_host(lib):
+    """gp_server_create rejects a bad configuration before it creates any
+    stream: ragged micro-batches are FP64 only and take no graphs."""
+    from paper_1203_1269_amd import binding, serving
+    L = serving._bind()
+    vp = ctypes.c_void_p
+    arr = (binding.GPDataset * 1)(_ds(n=300, d=3))
+    h = vp()
+
+    def create(**kw):
+        c = dict(max_batch=8, nstreams=2, prec=0, graphs=0, ragged=0)
+        c.update(kw)
+        cfg = serving.GPServerConfig(c["max_batch"], c["nstreams"], c["prec"], c["graphs"],
+                                     c["ragged"])
+        return L.gp_server_create(arr, 1, vp(1 << 24), 1 << 30, ctypes.byref(cfg), ctypes.byref(h))
+    assert create(ragged=1, prec=1) == binding.GP_EINVAL
+    assert create(ragged=1, prec=2) == binding.GP_EINVAL
+    assert create(ragged=1, graphs=1) == binding.GP_EINVAL
+    assert create(ragged=2) == binding.GP_EINVAL
+    assert create(graphs=2) == binding.GP_EINVAL
+    assert create(max_batch=0) == binding.GP_EINVAL
+    assert create(nstreams=65) == binding.GP_EINVAL
