@@ -25,16 +25,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # The request-server leg keeps up to 8 micro-batches in flight on as many
-# streams (plus the library's side streams); HIP maps a process's streams
-# onto 4 hardware queues unless told otherwise (the usual environment says 4
-# explicitly), which serialises the excess.  At least 8, set before the HIP
-# runtime starts (first device call).
+# streams, each with the library's two side streams; HIP maps a process's
+# streams onto 4 hardware queues unless told otherwise (the usual environment
+# says 4 explicitly), which serialises the excess.  At least 16, set before
+# the HIP runtime starts (first device call).
 try:
     _hwq = int(os.environ.get("GPU_MAX_HW_QUEUES", "4"))
 except ValueError:
     _hwq = 4
-if _hwq < 8:
-    os.environ["GPU_MAX_HW_QUEUES"] = "8"
+if _hwq < 16:
+    os.environ["GPU_MAX_HW_QUEUES"] = "16"
 
 METRIC = "-2logL evals/sec at n=4096,d=8 (mixed vs FP64 GPU); p50/p99 request latency"
 FP64_MFMA_PEAK = 78.6e12   # MI355X dense FP64 matrix peak, FLOP/s
@@ -246,7 +246,7 @@ def serving_leg(args, dev):
 
     out = {"datasets": len(ds), "arena_gb": args.serving_arena_gb,
            "hw_queues": os.environ.get("GPU_MAX_HW_QUEUES")}
-    out["ragged"] = run((0.5, 0.9), max_batch=96, nstreams=2, ragged=True)
+    out["ragged"] = run((0.5, 0.9), max_batch=128, nstreams=3, ragged=True)
     out["by_dataset"] = run((0.5, 0.9), max_batch=16, nstreams=8)
     out["by_dataset_graphs"] = run((0.5,), max_batch=16, nstreams=8, graphs=True)
     return out
