@@ -214,8 +214,8 @@ def serving_leg(args, dev):
     d in 2..12, p in {1.5, 1.95, 2}); for each form of micro-batch a
     closed-loop burst measures the saturation throughput, then Poisson
     streams at 0.5x and 0.9x of it are replayed open-loop with per-request
-    latency.  Forms: ragged (the oldest requests of any datasets in one
-    ragged launch sequence), one dataset per micro-batch, and the latter
+    latency.  Forms: ragged (requests of up to 8 datasets of close orders in
+    one ragged launch sequence), one dataset per micro-batch, and the latter
     launched as captured graphs (burst and 0.5x only)."""
     import numpy as np
     from paper_1203_1269_amd import binding, inputs, serving

@@ -325,10 +325,11 @@ gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
  *   and launches queued work while a stream and arena space are free: the
  *   oldest request picks the dataset, up to max_batch queued requests of it
  *   (arrival order) form the batch, shrunk until it fits; with `ragged`, up
- *   to max_batch queued requests of at most 8 datasets, taken in arrival
- *   order with the oldest request's dataset first (several requests of one
- *   dataset share the correlation build's power terms), form the batch
- *   (shrunk from the newest until it fits) and run as one ragged FP64 batch.  Returns the number
+ *   to max_batch queued requests (arrival order) of at most 8 datasets, the
+ *   oldest request's and those closest to it in order n (several requests
+ *   of one dataset share the correlation build's power terms), form the
+ *   batch (shrunk from the newest until it fits) and run as one ragged FP64
+ *   batch.  Returns the number
  *   of completions written or a negative gp_status.  A result of a batch whose
  *   launch failed has info = -4.
  * gp_server_outstanding: requests queued or on the GPU.

@@ -11,21 +11,20 @@
 //      gp_nll_batch, result download, event).
 // With `ragged` (FP64), a micro-batch mixes datasets and runs as one ragged
 // batch (nll_ragged_impl), whose kernels advance every request of the batch
-// together, each matrix at its own order.  It is filled in arrival order
-// from the queue with requests of at most RAGGED_DATASETS datasets, the
-// oldest request's first: when the queue is long this gathers several
-// requests per dataset, whose correlation builds then share the |x_i - x_j|^p
-// terms (one request per dataset shares nothing, and the build's pow() is
-// then a large part of the work); when it is short the batch is just the
-// oldest requests.  A request is overtaken only by requests of datasets
-// already in the batch of an older request, at most max_batch - 1 of them
-// per micro-batch.
+// together, each matrix at its own order.  It takes the requests (in arrival
+// order) of at most RAGGED_DATASETS datasets: the oldest request's, then
+// those closest to it in order n among the queued ones (choose_ragged_batch).
+// When the queue is long this gathers several requests per dataset, whose
+// correlation builds then share the |x_i - x_j|^p terms (one request per
+// dataset shares nothing, and the build's pow() is then a large part of the
+// work), and matrices of close orders, which finish together; when it is
+// short the batch is just the queued requests.
 // Micro-batches run concurrently on different streams,
 // so requests that arrive while others are on the GPU start as soon as a
 // stream and memory are free.  Every theta's arithmetic is independent of the
 // rest of its batch and of the other streams, so a request's result is
-// bitwise the one it gets alone.  Admission is strictly in arrival order of
-// the oldest request (no overtaking), so no request starves.
+// bitwise the one it gets alone.  Every micro-batch takes the oldest queued
+// request, so no request starves.
 //
 // With graphs on, each micro-batch's kernel sequence is captured into a HIP
 // graph and launched as one: the executable graph of a stream is kept and,
@@ -42,6 +41,7 @@
 #include <deque>
 #include <vector>
 
+#include "admission.hpp"
 #include "arena.hpp"
 #include "kernels.hpp"
 
@@ -334,22 +334,14 @@ int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
         st.busy = false;
     }
     // 2. admit queued work, oldest first
+    auto dataset_of = [sv](size_t q) { return sv->pending[q].dataset; };
     for (auto &st : sv->streams) {
         if (st.busy) continue;
         if (sv->pending.empty()) break;
         if (sv->ragged) {
-            // in arrival order, requests of at most RAGGED_DATASETS datasets
-            // (the oldest request's first), up to max_batch
-            std::vector<int> chosen;
-            std::vector<size_t> taken;
-            for (size_t q = 0; q < sv->pending.size() && (int)taken.size() < sv->max_batch; ++q) {
-                const int k = sv->pending[q].dataset;
-                if (std::find(chosen.begin(), chosen.end(), k) == chosen.end()) {
-                    if ((int)chosen.size() == RAGGED_DATASETS) continue;
-                    chosen.push_back(k);
-                }
-                taken.push_back(q);
-            }
+            std::vector<size_t> taken = choose_ragged_batch(
+                sv->pending.size(), dataset_of, [sv](int k) { return sv->ds[k].n; },
+                sv->max_batch, RAGGED_DATASETS);
             // shrunk (newest out) until its footprint fits
             bool launched = false;
             while (!taken.empty()) {
@@ -375,13 +367,10 @@ int32_t gp_server_poll(gp_server *sv, gp_completion *out, int32_t max_out)
             continue;
         }
         const int k = sv->pending.front().dataset;
+        std::vector<size_t> taken = choose_dataset_batch(sv->pending.size(), dataset_of,
+                                                         sv->max_batch);
         std::vector<gp_request> batch;
-        std::vector<size_t> taken;
-        for (size_t q = 0; q < sv->pending.size() && (int)batch.size() < sv->max_batch; ++q)
-            if (sv->pending[q].dataset == k) {
-                batch.push_back(sv->pending[q]);
-                taken.push_back(q);
-            }
+        for (size_t q : taken) batch.push_back(sv->pending[q]);
         // shrink the batch until its footprint fits the free arena space
         bool launched = false;
         while (!batch.empty()) {

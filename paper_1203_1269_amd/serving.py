@@ -59,8 +59,9 @@ class Server:
     """Resident datasets + a device arena (admission by HBM footprint) +
     `nstreams` concurrent micro-batches of at most `max_batch` thetas;
     `graphs` launches each micro-batch as a captured HIP graph; `ragged`
-    (FP64) forms each micro-batch from the oldest requests of any datasets
-    and runs it as one ragged batch."""
+    (FP64) forms each micro-batch from the requests of up to 8 datasets (the
+    oldest request's and those closest to it in order n) and runs it as one
+    ragged batch."""
 
     def __init__(self, datasets, arena_bytes: int, max_batch: int = 16, nstreams: int = 8,
                  prec: str = "fp64", device="cuda", graphs: bool = False, ragged: bool = False):
