@@ -216,9 +216,9 @@ def multi_leg(args, dev, per=16):
 def serving_leg(args, dev):
     """64 resident datasets (n uniform over multiples of 64 in [256, 6144],
     d in 2..12, p in {1.5, 1.95, 2}); for each form of micro-batch a
-    closed-loop burst measures the saturation throughput, then Poisson
-    streams at 0.5x and 0.9x of it are replayed open-loop with per-request
-    latency.  Forms: ragged (requests of up to 8 datasets of close orders in
+    closed-loop burst (one untimed pass, then two timed) measures the
+    saturation throughput, then Poisson streams at 0.5x and 0.9x of it are replayed
+    open-loop with per-request latency.  Forms: ragged (requests of up to 8 datasets of close orders in
     one ragged launch sequence), one dataset per micro-batch, and the latter
     launched as captured graphs (burst and 0.5x only)."""
     import numpy as np
@@ -231,9 +231,15 @@ def serving_leg(args, dev):
 
     def run(fracs, **cfg):
         srv = serving.Server(ds, arena_bytes=arena, **cfg)
-        lat, _, bsz, wall = serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
-                                           [r[1] for r in burst])
-        sat = len(burst) / wall
+        # one untimed pass of the burst first (a new server's streams, their
+        # side streams and staging buffers are set up on first use), then
+        # two timed passes
+        serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst], [r[1] for r in burst])
+        wall = 0.0
+        for _ in range(2):
+            wall += serving.replay(srv, [0.0] * len(burst), [r[2] for r in burst],
+                                   [r[1] for r in burst])[3]
+        sat = 2 * len(burst) / wall
         out = dict(cfg)
         out["saturation_evals_per_s"] = sat
         for frac in fracs:
