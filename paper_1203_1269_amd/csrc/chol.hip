@@ -769,8 +769,10 @@ void launch_syrk_update(double *A, int lda, size_t bstride, int np, int cs, int 
 namespace {
 
 // Side streams (and their events) of one caller stream, created on first use
-// per (device, caller stream) and kept for the life of the process: `s` for
-// the lookahead trailing updates, `solve` for the solve segments.  Default
+// per (device, caller stream) and kept until release_side_streams(caller)
+// (the request server calls it for each of its streams before destroying
+// them) or the end of the process: `s` for the lookahead trailing updates,
+// `solve` for the solve segments.  Default
 // priority, non-blocking.  At most SIDE_CALLERS caller streams get them;
 // calls on further streams factor without the lookahead (same results), so a
 // caller that cycles through new streams does not make the library create
@@ -783,10 +785,13 @@ struct SideStream {
     hipEvent_t panel = nullptr, solved = nullptr;
 };
 
+std::mutex side_mu;
+std::map<std::pair<int, hipStream_t>, SideStream> side_table;
+
 SideStream *side_for(hipStream_t caller)
 {
-    static std::mutex mu;
-    static std::map<std::pair<int, hipStream_t>, SideStream> table;
+    std::mutex &mu = side_mu;
+    auto &table = side_table;
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) return nullptr;
     std::lock_guard<std::mutex> lock(mu);
@@ -810,6 +815,27 @@ SideStream *side_for(hipStream_t caller)
 }
 
 }  // namespace
+
+void release_side_streams(hipStream_t caller)
+{
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return;
+    std::lock_guard<std::mutex> lock(side_mu);
+    auto it = side_table.find(std::make_pair(dev, caller));
+    if (it == side_table.end()) return;
+    SideStream &sd = it->second;
+    if (sd.s) {
+        (void)hipStreamSynchronize(sd.s);
+        (void)hipStreamSynchronize(sd.solve);
+        (void)hipEventDestroy(sd.fork);
+        (void)hipEventDestroy(sd.join);
+        (void)hipEventDestroy(sd.panel);
+        (void)hipEventDestroy(sd.solved);
+        (void)hipStreamDestroy(sd.s);
+        (void)hipStreamDestroy(sd.solve);
+    }
+    side_table.erase(it);
+}
 
 // Blocked right-looking Cholesky with a one-panel lookahead: after outer
 // panel [c, pe) is factored, the trailing update is split at the end of the

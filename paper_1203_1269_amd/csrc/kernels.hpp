@@ -178,6 +178,11 @@ struct SolvePlan {
 // `bordered`, A has order 2 np and holds [[R, I], [I, 0]]; only the first np
 // columns are factored, which leaves L^-T bottom-left and -R^-1 bottom-right.
 // With a solve plan the forward solves and eq. 3-4 are done as well.
+// Synchronizes and destroys the side streams the factorisation created for
+// caller stream `caller` on the current device (if any), before the caller
+// destroys that stream.
+void release_side_streams(hipStream_t caller);
+
 void factor_batch(double *A, int lda, size_t bstride, int np, int batch, int32_t *info,
                   double *lpart, double *lk, hipStream_t s, int prec, bool bordered = false,
                   const uint8_t *mask = nullptr, int8_t *crt_res = nullptr,

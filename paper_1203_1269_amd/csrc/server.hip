@@ -398,7 +398,10 @@ gp_status gp_server_destroy(gp_server *sv)
         if (st.s) (void)hipStreamSynchronize(st.s);
         if (st.exec) (void)hipGraphExecDestroy(st.exec);
         if (st.done) (void)hipEventDestroy(st.done);
-        if (st.s) (void)hipStreamDestroy(st.s);
+        if (st.s) {
+            release_side_streams(st.s);
+            (void)hipStreamDestroy(st.s);
+        }
         if (st.h_theta) (void)hipHostFree(st.h_theta);
         if (st.h_out) (void)hipHostFree(st.h_out);
     }

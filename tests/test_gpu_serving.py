@@ -3,8 +3,8 @@ exactly once, each result is bitwise the one the request gets alone and
 within the FP64 bar of the 80-bit oracle, work of different datasets
 overlaps (several micro-batches in flight), admission respects the arena
 (HBM footprint) and a tiny arena queues instead of failing.  Both forms of
-micro-batch: one dataset each, and ragged (the oldest requests of any
-datasets in one launch sequence)."""
+micro-batch: one dataset each, and ragged (requests of several datasets of
+close orders in one launch sequence)."""
 import numpy as np
 import pytest
 
@@ -49,6 +49,25 @@ def test_server_results_match_alone(env, ragged):
     if ragged:   # micro-batches mixed datasets
         assert len({reqs[q][1] for q in range(8)}) > 1
     print(serving.latency_summary(lat, wall))
+
+
+def test_ragged_servers_created_and_destroyed(env):
+    """Servers made and closed one after another (each close releases the
+    side streams the factorisation made for its streams; the next server's
+    streams may reuse their handles): results stay bitwise the alone ones."""
+    binding, serving, sets, ds = env
+    reqs = inputs.serving_requests(sets, count=60, rate=1e9, seed=43)
+    for rep in range(4):
+        print(f"[serving] server {rep} of 4, ragged, created and destroyed", flush=True)
+        srv = serving.Server(ds, arena_bytes=2 << 30, max_batch=16, nstreams=3, ragged=True)
+        lat, res, bsz, wall = serving.replay(srv, [r[0] for r in reqs], [r[2] for r in reqs],
+                                             [r[1] for r in reqs], time_limit=60)
+        assert srv.outstanding() == 0 and srv.arena_used() == 0
+        srv.close()
+        for q in range(rep, 60, 13):
+            a = alone(binding, ds, reqs[q][1], reqs[q][2])
+            for key in ("logdet", "mu", "sigma2", "nll"):
+                assert res[q][key] == a[key], (rep, q, key)
 
 
 @pytest.mark.parametrize("ragged", [False, True])
