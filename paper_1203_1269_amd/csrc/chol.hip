@@ -806,7 +806,12 @@ SideStream *side_for(hipStream_t caller)
         hipStreamCreateWithFlags(&sd.solve, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&sd.panel, hipEventDisableTiming) != hipSuccess ||
         hipEventCreateWithFlags(&sd.solved, hipEventDisableTiming) != hipSuccess) {
-        // no lookahead for this stream; remember the failure
+        // no lookahead for this stream; free what was made, remember the failure
+        for (hipEvent_t e : {sd.fork, sd.join, sd.panel, sd.solved})
+            if (e) (void)hipEventDestroy(e);
+        for (hipStream_t st : {sd.s, sd.solve})
+            if (st) (void)hipStreamDestroy(st);
+        (void)hipGetLastError();
         table[key] = SideStream{};
         return nullptr;
     }
