@@ -238,7 +238,7 @@ gp_status gp_cholesky_batch(int32_t n, int32_t batch, double *A, int32_t lda, in
 
 struct GradLayout {
     int np, ntiles;
-    size_t lda, bstride, mat, lpart, info, lk, alpha, part, total;
+    size_t lda, bstride, mat, lpart, info, lk, z, alpha, part, total;
 };
 
 static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
@@ -259,6 +259,8 @@ static bool grad_layout_for(int n, int d, int batch, GradLayout &L)
     off = align_up(off + sizeof(int32_t) * (size_t)batch);
     L.lk = off;
     off = align_up(off + sizeof(double) * TB * TB * (size_t)batch);
+    L.z = off;
+    off = align_up(off + sizeof(double) * 2 * (size_t)L.np * batch);
     L.alpha = off;
     off = align_up(off + sizeof(double) * (size_t)L.np * batch);
     L.part = off;
@@ -334,10 +336,11 @@ gp_status gp_nll_grad(const gp_dataset *ds, int32_t batch, const double *theta, 
     launch_corr_build(ds->X, ds->n, ds->d, family_p(ds), ds->delta, theta, batch, A, lda,
                       L.bstride, np, stream);
     launch_border_init(A, lda, L.bstride, np, batch, stream);
+    // the forward solves and eq. 3-4 follow the factorisation panel by panel
+    // (solve segments on their own stream, reading only the top n_pad rows)
+    SolvePlan plan{ds->y, ds->n, (double *)(base + L.z), out};
     factor_batch(A, lda, L.bstride, np, batch, info, lpart, (double *)(base + L.lk), stream,
-                 GP_FP64, true);
-    launch_solve_reduce(A, lda, L.bstride, np, ds->n, ds->y, lpart, np / TB, info, batch, out,
-                        stream);
+                 GP_FP64, true, nullptr, nullptr, nullptr, true, 0, &plan);
     launch_alpha(A, lda, L.bstride, np, ds->n, ds->y, out, alpha, batch, stream);
     launch_adjoint(A, lda, L.bstride, np, ds->n, ds->d, family_p(ds), ds->X, theta, alpha, out,
                    part, grad, batch, stream);
