@@ -333,7 +333,8 @@ gp_status gp_nll_multi(const gp_dataset *ds, int32_t nds, const int32_t *counts,
  *   of completions written or a negative gp_status.  A result of a batch whose
  *   launch failed has info = -4.
  * gp_server_outstanding: requests queued or on the GPU.
- * gp_server_destroy: waits for the streams, frees host resources.
+ * gp_server_destroy: waits for the streams, frees host resources and the
+ *   streams the factorisation made beside the server's streams.
  * One host thread drives a server. */
 typedef struct gp_server gp_server;
 typedef struct {
